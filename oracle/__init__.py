@@ -1,0 +1,213 @@
+"""CPU oracle (plain FP64 C, orc_mhd.c) for the heliospheric ideal-MHD update.
+
+TEST INFRASTRUCTURE ONLY: imported by tests/, the smoke check and the bench's
+CPU-baseline leg.  The product library never loads it.  It shares no code
+with the HIP path; both read the same seeded inputs (paper_2501_15923_amd.synth).
+
+Build: ``python -m oracle.build`` (or ``__graft_entry__.build()``) compiles
+orc_mhd.c with ``gcc -O2 -ffp-contract=off -fopenmp`` into liborc_mhd.so.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "liborc_mhd.so")
+SRC_PATH = os.path.join(_HERE, "orc_mhd.c")
+
+GEOM_SPH, GEOM_SLAB = 0, 1
+FLUX_TVDLF, FLUX_HLL = 0, 1
+LIM_MINMOD, LIM_MC = 0, 1
+BCT_MAP, BCT_ASYMM = 0, 1
+BCM_DRIVEN, BCM_FROZEN = 0, 1
+SLABX_OUTFLOW, SLABX_PERIODIC = 0, 1
+PRIM_SI, CONS_CODE, CONS_PADDED, PRIM_CODE = 0, 1, 2, 3
+
+
+def build(force: bool = False) -> str:
+    if force or not os.path.exists(LIB_PATH) or \
+            os.path.getmtime(LIB_PATH) < os.path.getmtime(SRC_PATH):
+        tmp = LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-fopenmp",
+                               "-ffp-contract=off", "-fPIC", "-shared",
+                               "-Wall", "-o", tmp, SRC_PATH, "-lm"])
+        os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build()
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        D = ctypes.POINTER(ctypes.c_double)
+        I = ctypes.POINTER(ctypes.c_int)
+        L.orc_create.restype = P
+        L.orc_create.argtypes = [I, D]
+        L.orc_destroy.argtypes = [P]
+        L.orc_units.argtypes = [D]
+        L.orc_edges.argtypes = [P, D, D, D]
+        L.orc_set_maps.argtypes = [P, ctypes.c_int, D, D]
+        L.orc_set_cmes.argtypes = [P, ctypes.c_int, D]
+        L.orc_init_radial.argtypes = [P]
+        L.orc_set_state.argtypes = [P, D, ctypes.c_int]
+        L.orc_get_state.argtypes = [P, D, ctypes.c_int]
+        L.orc_step.argtypes = [P, ctypes.c_int, ctypes.c_double, D]
+        L.orc_dt.restype = ctypes.c_double
+        L.orc_dt.argtypes = [P]
+        L.orc_get_clock.argtypes = [P, D]
+        L.orc_set_clock.argtypes = [P, ctypes.c_double, ctypes.c_long]
+        L.orc_set_clock_code.argtypes = [P, ctypes.c_double, ctypes.c_long]
+        L.orc_fill_ghosts.argtypes = [P, ctypes.c_double, D]
+        L.orc_inner_boundary.argtypes = [P, ctypes.c_double, D]
+        L.orc_last_boundary_flux.argtypes = [P, D]
+        L.orc_volumes.argtypes = [P, D]
+        L.orc_sample.argtypes = [P, ctypes.c_int, ctypes.c_int, D, D]
+        L.orc_divb.argtypes = [P, D]
+        _lib = L
+    return _lib
+
+
+def _d(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def units() -> dict:
+    out = np.zeros(6)
+    lib().orc_units(_d(out))
+    return dict(t=out[0], L=out[1], rho=out[2], p=out[3], B=out[4], v=out[5])
+
+
+class Oracle:
+    """One oracle run.  Spherical: radii in metres, angles in radians, maps /
+    CMEs / probe tables in SI.  Slab: box edges in code units."""
+
+    def __init__(self, nr, nt, nph, *, geom=GEOM_SPH, r_in=None, r_out=None,
+                 th_min=None, th_max=None, gamma=1.5, omega=2.87e-6, cfl=0.4,
+                 flux=FLUX_TVDLF, limiter=LIM_MINMOD, gravity=True, corot=True,
+                 bc_transverse=BCT_MAP, bc_mode=BCM_DRIVEN,
+                 slab_bcx=SLABX_OUTFLOW, box=(0, 1, 0, 1, 0, 1)):
+        from paper_2501_15923_amd import synth
+        self.nr, self.nt, self.np_ = nr, nt, nph
+        self.geom = geom
+        ip = np.array([nr, nt, nph, geom, flux, limiter, int(gravity),
+                       int(corot), bc_transverse, bc_mode, slab_bcx],
+                      dtype=np.int32)
+        dp = np.array([
+            synth.AU * 0.1 if r_in is None else r_in,
+            synth.AU * 2.0 if r_out is None else r_out,
+            synth.DEG * 30 if th_min is None else th_min,
+            synth.DEG * 150 if th_max is None else th_max,
+            gamma, omega, cfl, *box], dtype=np.float64)
+        self._ip, self._dp = ip, dp
+        self.h = lib().orc_create(ip.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _d(dp))
+        if not self.h:
+            raise MemoryError("orc_create failed")
+        self.gamma = gamma
+
+    def __del__(self):
+        h = getattr(self, "h", None)
+        if h:
+            lib().orc_destroy(h)
+            self.h = None
+
+    @property
+    def shape(self):
+        return (8, self.np_, self.nt, self.nr)
+
+    @property
+    def padded_shape(self):
+        return (8, self.np_ + 4, self.nt + 4, self.nr + 4)
+
+    def edges(self):
+        r = np.zeros(self.nr + 1)
+        t = np.zeros(self.nt + 1)
+        p = np.zeros(self.np_ + 1)
+        lib().orc_edges(self.h, _d(r), _d(t), _d(p))
+        return r, t, p
+
+    def set_maps(self, times, maps):
+        times = np.ascontiguousarray(times, dtype=np.float64)
+        maps = np.ascontiguousarray(maps, dtype=np.float64)
+        rc = lib().orc_set_maps(self.h, len(times), _d(times), _d(maps))
+        if rc:
+            raise ValueError(f"orc_set_maps rejected the maps ({rc})")
+
+    def set_cmes(self, rows):
+        rows = np.ascontiguousarray(np.atleast_2d(rows), dtype=np.float64)
+        n = 0 if rows.size == 0 else rows.shape[0]
+        lib().orc_set_cmes(self.h, n, _d(rows))
+
+    def init_radial(self):
+        if lib().orc_init_radial(self.h):
+            raise RuntimeError("orc_init_radial needs maps and spherical geometry")
+
+    def set_state(self, a, kind=PRIM_SI):
+        a = np.ascontiguousarray(a, dtype=np.float64)
+        lib().orc_set_state(self.h, _d(a), kind)
+
+    def get_state(self, kind=PRIM_SI):
+        out = np.zeros(self.padded_shape if kind == CONS_PADDED else self.shape)
+        lib().orc_get_state(self.h, _d(out), kind)
+        return out
+
+    def step(self, n, t_end=-1.0):
+        info = np.zeros(6)
+        lib().orc_step(self.h, int(n), float(t_end), _d(info))
+        return dict(steps=int(info[0]), t=info[1], dt=info[2], resid=info[3],
+                    status=int(info[4]), bad_cell=int(info[5]))
+
+    def dt(self):
+        return lib().orc_dt(self.h)
+
+    def clock(self):
+        out = np.zeros(5)
+        lib().orc_get_clock(self.h, _d(out))
+        return dict(t=out[0], step=int(out[1]), dt=out[2], resid=out[3], t_code=out[4])
+
+    def set_clock(self, t, step=0):
+        lib().orc_set_clock(self.h, float(t), int(step))
+
+    def set_clock_code(self, t_code, step=0):
+        lib().orc_set_clock_code(self.h, float(t_code), int(step))
+
+    def fill_ghosts(self, t):
+        out = np.zeros(self.padded_shape)
+        lib().orc_fill_ghosts(self.h, float(t), _d(out))
+        return out
+
+    def inner_boundary(self, t):
+        out = np.zeros((8, self.nt, self.np_))
+        lib().orc_inner_boundary(self.h, float(t), _d(out))
+        return out
+
+    def last_boundary_flux(self):
+        out = np.zeros(8)
+        lib().orc_last_boundary_flux(self.h, _d(out))
+        return out
+
+    def volumes(self):
+        out = np.zeros((self.np_, self.nt, self.nr))
+        lib().orc_volumes(self.h, _d(out))
+        return out
+
+    def sample(self, traj):
+        traj = np.ascontiguousarray(traj, dtype=np.float64)
+        n, npts = traj.shape[0], traj.shape[1]
+        out = np.zeros((n, 12))
+        lib().orc_sample(self.h, n, npts, _d(traj), _d(out))
+        return out
+
+    def divb(self):
+        out = np.zeros((self.np_, self.nt, self.nr))
+        lib().orc_divb(self.h, _d(out))
+        return out

@@ -1,0 +1,56 @@
+"""Workload presets (synthetic stand-ins for the paper's coronal-model driven
+runs; see synth.py for how each input is drawn).
+
+  tiny_static   64 x 16 x 32 cells, one static map, 200 RK2 steps, CFL 0.4
+  prod_dynamic  600 x 60 x 120 cells, 10 maps 6 h apart, 3 simulated days,
+                4 probe trajectories
+  prod_cme      prod_dynamic plus one cone CME (1000 km/s, 30 deg, 8 h)
+"""
+from __future__ import annotations
+
+import dataclasses
+
+import numpy as np
+
+from . import synth
+from .synth import DAY, HOUR, Grid
+
+
+@dataclasses.dataclass
+class Workload:
+    name: str
+    grid: Grid
+    times: np.ndarray      # [n_maps] s
+    maps: np.ndarray       # [n_maps][8][nt][np] SI primitives
+    cmes: np.ndarray       # [n_cme][8]
+    probes: np.ndarray | None  # [n][npts][4]
+    steps: int
+    t_end: float           # s, <= 0: none
+    gamma: float = 1.5
+    omega: float = synth.OMEGA_SUN
+    cfl: float = 0.4
+    probe_cadence: float = 0.0  # s; 0: every step
+
+
+def tiny_static(seed: int = 0) -> Workload:
+    g = Grid(64, 16, 32)
+    m = synth.static_map(g, seed)[None]
+    return Workload("tiny_static_64x16x32", g, np.zeros(1), m,
+                    np.zeros((0, 8)), None, 200, -1.0)
+
+
+def prod_dynamic(seed: int = 1, nr: int = 600, nt: int = 60, nph: int = 120) -> Workload:
+    g = Grid(nr, nt, nph)
+    times, maps = synth.dynamic_maps(g, seed)
+    probes = synth.probe_tables(3 * DAY, seed)
+    return Workload(f"prod_dynamic_{nr}x{nt}x{nph}", g, times, maps,
+                    np.zeros((0, 8)), probes, 0, 3 * DAY)
+
+
+def prod_cme(seed: int = 2, nr: int = 600, nt: int = 60, nph: int = 120) -> Workload:
+    w = prod_dynamic(1, nr, nt, nph)
+    cme = synth.cone_cme(seed, w.probes[1])
+    w.name = f"prod_cme_{nr}x{nt}x{nph}"
+    w.cmes = cme[None]
+    w.probe_cadence = 600.0
+    return w
