@@ -1,0 +1,241 @@
+/*
+ * icarus_hip.h -- C-ABI of the MI355X heliospheric ideal-MHD library.
+ *
+ * The library advances the solar wind in the frame co-rotating with the Sun
+ * on a radially stretched spherical grid starting at the 0.1 AU inner
+ * boundary (Icarus 3.0, arXiv 2501.15923):
+ *   - ideal MHD, Sect. 2 Eqs. (1)-(6), mu0 = 1 in code units, gravity and the
+ *     centrifugal + Coriolis force F with energy source v.F, rotation rate
+ *     Omega taken from the parameters (Sect. 2);
+ *   - inner boundary from primitive-variable boundary maps (Sect. 2.1), the
+ *     same value in every ghost layer (Sect. 2.1), linear interpolation in
+ *     time between successive maps (Sect. 3), cone CMEs written only into
+ *     the boundary points inside the cone (Sect. 3.2, bc_icarus);
+ *   - initial state by radial expansion of the first map (Sect. 2.1);
+ *   - sampling along spacecraft trajectories interpolated from tables
+ *     (Sect. 2, particle sampling on stretched grids).
+ * The finite-volume scheme (not printed in the paper): primitive MUSCL
+ * reconstruction with a minmod or MC limiter, TVD-Lax-Friedrichs or HLL face
+ * fluxes, exact spherical finite-volume divergence with area-difference
+ * pressure sources, SSP-RK2 in time, dt = CFL / max over cells of
+ * sum_d (|v_d| + c_f,d) / dx_d.
+ *
+ * Conventions
+ *   - Every call returns ICR_OK (0) or a negative ICR_ERR_* code; the message
+ *     of the last failure on the calling thread is icr_last_error().
+ *   - Arguments are validated on the host before any GPU work.
+ *   - Host inputs are copied; the caller keeps ownership of every buffer it
+ *     passes.  Device memory for the solver comes from the caller: query
+ *     icr_workspace_bytes(), allocate that many bytes of device memory
+ *     (256-byte aligned) and keep it alive until icr_destroy().
+ *   - API quantities are SI: metres, seconds, kg/m^3, m/s, Pa, tesla,
+ *     radians.  theta is colatitude, phi longitude in the co-rotating frame.
+ *   - Primitive channel order (maps and states):
+ *       rho, v_r, v_theta, v_phi (co-rotating frame), p, B_r, B_theta, B_phi.
+ *   - Layouts: maps [n_maps][8][n_theta][n_phi]; states [8][n_phi][n_theta][n_r]
+ *     (active cells only, r fastest); all row-major, float64 at the ABI.
+ *   - Work is enqueued on the HIP stream given at creation; calls that return
+ *     host data synchronise that stream.
+ *   - A solver is not thread-safe: one host thread at a time per solver.
+ */
+#ifndef ICARUS_HIP_H
+#define ICARUS_HIP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum {
+  ICR_OK = 0,
+  ICR_ERR_ARG = -1,          /* invalid argument (size, range, ordering)   */
+  ICR_ERR_STATE = -2,        /* call out of order (e.g. step before maps)  */
+  ICR_ERR_NONPHYSICAL = -3,  /* rho <= 0, p <= 0 or non-finite value found */
+  ICR_ERR_HIP = -4,          /* HIP runtime failure                         */
+  ICR_ERR_UNSUPPORTED = -5   /* option not implemented                      */
+};
+
+enum { ICR_FLUX_TVDLF = 0, ICR_FLUX_HLL = 1 };
+enum { ICR_LIM_MINMOD = 0, ICR_LIM_MC = 1 };
+enum { ICR_PREC_F64 = 64, ICR_PREC_F32 = 32 };
+
+/* State kinds for icr_set_state / icr_get_state. */
+enum {
+  ICR_STATE_PRIM_SI = 0,   /* primitive, SI units, float64                */
+  ICR_STATE_CONS_CODE = 1  /* conservative, code units, float64           */
+};
+
+/* Grid and capacities.  The radial edges are r_in * q^i, q = (r_out /
+ * r_in)^(1/n_r) (radially stretched grid, Sect. 2); colatitude uniform on
+ * [th_min, th_max]; longitude uniform and periodic on [0, 2 pi).  The
+ * capacities size the workspace: boundary maps, cone CMEs, probes, points
+ * per trajectory table and rows of the device probe log. */
+typedef struct {
+  int n_r, n_theta, n_phi;
+  double r_in, r_out;        /* m, 0 < r_in < r_out                     */
+  double th_min, th_max;     /* rad, 0 < th_min < th_max < pi           */
+  int max_maps;              /* >= 1                                     */
+  int max_cmes;              /* >= 0                                     */
+  int max_probes;            /* >= 0                                     */
+  int max_traj_pts;          /* >= 2 when max_probes > 0                 */
+  int probe_log_rows;        /* >= 0: rows of [max_probes][12] in the log */
+} icr_grid;
+
+/* Physics and numerics (Sect. 2: gamma = 1.5, co-rotating frame with the
+ * equatorial rotation rate, gravity of the Sun). */
+typedef struct {
+  double gamma;              /* adiabatic index, > 1                     */
+  double omega;              /* rotation rate, rad/s (0 = inertial)      */
+  double cfl;                /* Courant number, (0, 1]                   */
+  int flux;                  /* ICR_FLUX_*                               */
+  int limiter;               /* ICR_LIM_*                                */
+  int precision;             /* ICR_PREC_F64 or ICR_PREC_F32             */
+  int gravity;               /* 1: include -GM/r^2 e_r                   */
+  int corotation;            /* 1: centrifugal + Coriolis sources        */
+} icr_phys;
+
+/* Clock: time [s] since the map time origin, completed RK2 steps, the dt of
+ * the last step [s], the CFL dt the next step will use (before clipping)
+ * [s], the last relaxation residual ||rho^{n+1}-rho^n||_2/||rho^n||_2, and
+ * the time in code units for exact restarts (icr_set_clock_code). */
+typedef struct {
+  double t;
+  long long step;
+  double last_dt;
+  double next_dt;
+  double residual;
+  double t_code;
+} icr_clock;
+
+/* Result of icr_step.  bad_cell = -1, or the linear index k*n_theta*n_r +
+ * j*n_r + i of the first active cell found with rho <= 0, p <= 0 or a
+ * non-finite value after the step that produced it. */
+typedef struct {
+  int steps_taken;
+  int status;
+  long long bad_cell;
+  double t;
+  double last_dt;
+  double residual;
+} icr_step_info;
+
+typedef struct icr_solver icr_solver;
+
+/* Message of the last failed call on this thread ("" if none). */
+const char *icr_last_error(void);
+
+/* Code units: time, length, density, pressure, field, velocity (SI per code
+ * unit).  out: 6 doubles. */
+int icr_units(double *out);
+
+/* Device bytes the solver needs for this grid and physics. */
+int icr_workspace_bytes(const icr_grid *grid, const icr_phys *phys,
+                        size_t *bytes);
+
+/* Create a solver on the current HIP device.  dev_workspace: caller-owned
+ * device memory of at least icr_workspace_bytes(); hip_stream: a
+ * hipStream_t (NULL = default stream).  Computes the grid metric on the
+ * device.  The state is undefined until icr_init_radial or icr_set_state. */
+int icr_create(const icr_grid *grid, const icr_phys *phys, void *dev_workspace,
+               size_t workspace_bytes, void *hip_stream, icr_solver **out);
+
+/* Release the solver (not the caller's workspace).  NULL is allowed. */
+void icr_destroy(icr_solver *s);
+
+/* Grid edges: r [n_r+1] m, theta [n_theta+1] rad, phi [n_phi+1] rad.  Any
+ * pointer may be NULL. */
+int icr_grid_edges(const icr_solver *s, double *r_edges, double *th_edges,
+                   double *ph_edges);
+
+/* Boundary maps at 0.1 AU (Sect. 2.1 lookup table, Sect. 3 time series):
+ * n_maps <= max_maps primitive maps in SI, [n_maps][8][n_theta][n_phi],
+ * at strictly ascending times t_s [n_maps] (s).  Between two map times the
+ * boundary is the linear interpolation of the bracketing maps; before the
+ * first / after the last map time it is that map.  Requires rho > 0 and
+ * p > 0 everywhere (ICR_ERR_ARG otherwise).  maps_on_device: 1 if maps_si
+ * is a device pointer (t_s is always host). */
+int icr_set_boundary_maps(icr_solver *s, int n_maps, const double *t_s,
+                          const double *maps_si, int maps_on_device);
+
+/* Cone CMEs (Sect. 3.2 bc_icarus; Table 1 parameters): n <= max_cmes rows
+ * of 8 SI values: insertion start [s], duration [s], latitude [rad],
+ * co-rotating longitude [rad], half-width [rad], speed [m/s], density
+ * [kg/m^3], temperature [K].  While t_start <= t < t_start + duration the
+ * boundary points whose great-circle distance to the cone axis is <= the
+ * half-width get rho, v_r = speed, v_theta = 0, v_phi = -Omega r_in
+ * sin(theta), p = 2 (rho/m_p) k_B T; B is unchanged (the cone CME is not
+ * magnetised).  n = 0 removes all CMEs. */
+int icr_set_cmes(icr_solver *s, int n, const double *rows);
+
+/* Initial state by radial expansion of the first map (Sect. 2.1):
+ * rho ~ r^-2, v_r constant, v_theta = 0, v_phi = -Omega r sin(theta),
+ * p ~ r^(-2 gamma), B_r ~ r^-2, B_theta = 0, B_phi ~ r^-1, from r_in.
+ * Sets the clock to t = 0, step 0 and computes the first dt. */
+int icr_init_radial(icr_solver *s);
+
+/* Replace the state.  kind: ICR_STATE_*; data: [8][n_phi][n_theta][n_r]
+ * float64, host (on_device = 0) or device (on_device = 1) pointer.
+ * Recomputes the CFL dt; the clock time is kept. */
+int icr_set_state(icr_solver *s, const double *data, int kind, int on_device);
+
+/* Copy the state out (same layout and kinds as icr_set_state). */
+int icr_get_state(icr_solver *s, double *out, int kind, int on_device);
+
+int icr_get_clock(icr_solver *s, icr_clock *out);
+/* Set time [s] and step count; recomputes the CFL dt. */
+int icr_set_clock(icr_solver *s, double t, long long step);
+/* Set the time in code units (bit-exact restart from icr_clock.t_code). */
+int icr_set_clock_code(icr_solver *s, double t_code, long long step);
+
+/* Advance up to n_steps SSP-RK2 steps (n_steps >= 0).  If t_end_s > 0 the
+ * last step is shortened to land on t_end_s and no step starts at or after
+ * it.  The clock, dt and map bracket stay on the device; steps are replayed
+ * from captured HIP graphs; one host synchronisation per call.  Returns
+ * ICR_ERR_NONPHYSICAL (and stops advancing) when a step produced an
+ * invalid cell; info may be NULL. */
+int icr_step(icr_solver *s, int n_steps, double t_end_s, icr_step_info *info);
+
+/* Probes (Sect. 2 particle sampling): n <= max_probes trajectory tables
+ * traj [n][n_pts][4] of rows (t [s], r [m], theta, phi_inertial [rad]),
+ * ascending t, unwrapped phi, 2 <= n_pts <= max_traj_pts.  Positions are
+ * linear in t between rows (clamped outside), phi' = phi - Omega t.
+ * cadence_s: > 0 logs a record each time t crosses a multiple of cadence_s,
+ * = 0 logs after every step, < 0 disables the device log.  Clears the log. */
+int icr_set_probes(icr_solver *s, int n, int n_pts, const double *traj,
+                   double cadence_s);
+
+/* Sample every probe at the current time: out [n][12] host doubles: t, r,
+ * theta, phi', rho, v_r, v_theta, v_phi (inertial frame), p, B_r, B_theta,
+ * B_phi (SI), trilinear in (r, theta, phi) between the 8 surrounding cell
+ * centres.  Outside the range of cell centres the 8 plasma values are NaN. */
+int icr_sample_probes(icr_solver *s, double *out);
+
+/* Copy the device probe log to host: up to cap records, each [n][12] as in
+ * icr_sample_probes; *n_rec receives the number of records logged (may
+ * exceed cap; the log keeps the first probe_log_rows records). */
+int icr_read_probe_log(icr_solver *s, double *out, int cap, int *n_rec);
+
+/* Inner-boundary primitive (SI) the solver would impose at time t_s, after
+ * time interpolation and the CME overwrite: out [8][n_theta][n_phi] host. */
+int icr_boundary_at(icr_solver *s, double t_s, double *out);
+
+/* Launch configuration of the fused stage kernel: variant 0 = default,
+ * 1 = one thread per cell with on-the-fly neighbour primitives; tile
+ * (tile_r, tile_t) in {(64, 4), (128, 2), (256, 1)} (0 = default);
+ * use_graphs 0/1 replays steps from captured HIP graphs.  Every variant
+ * and tile gives bit-identical results. */
+int icr_set_launch(icr_solver *s, int variant, int tile_r, int tile_t,
+                   int use_graphs);
+
+/* Advance n_steps (> 0) steps with direct launches, timing each kernel with
+ * HIP events on the solver's stream.  avg_ms[4] receives the mean duration
+ * of the boundary driver, stage 1, stage 2 and the probe logger (0 if not
+ * launched).  Same results as icr_step. */
+int icr_profile_steps(icr_solver *s, int n_steps, double *avg_ms);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* ICARUS_HIP_H */

@@ -704,7 +704,8 @@ static double cfl_dt(const orc_ctx *c, const double *U) {
         double lam = 0.0;
         for (int d = 0; d < 3; ++d)
           lam += (fabs(w[d + 1]) + fast_speed(c->gamma, w, d + 1)) / dx[d];
-        if (!(lam <= lmax)) lmax = lam; /* NaN propagates into lmax */
+        if (lam > lmax) lmax = lam; /* invalid (NaN) cells are skipped; the
+                                       step's validity check reports them */
       }
   return c->cfl / lmax;
 }

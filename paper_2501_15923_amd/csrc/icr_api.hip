@@ -1,0 +1,807 @@
+// icr_api.hip -- host side of the C-ABI declared in include/icarus_hip.h.
+//
+// Owns argument validation, the device workspace layout, unit conversion of
+// the API's SI inputs, the device-resident step loop and its HIP-graph
+// replay.  All numerics run in the kernels of icr_kernels.hip.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "icarus_hip.h"
+#include "icr_kernels.hpp"
+
+using namespace icr;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+#define HIP_TRY(expr)                                                              \
+  do {                                                                             \
+    hipError_t e_ = (expr);                                                        \
+    if (e_ != hipSuccess)                                                          \
+      return fail(ICR_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));     \
+  } while (0)
+
+// ---- units: code value = SI value / unit ----------------------------------
+constexpr double kAU = 1.495978707e11;
+constexpr double kV = 1.0e5;
+constexpr double kMp = 1.67262192369e-27;
+constexpr double kKb = 1.380649e-23;
+constexpr double kMu0 = 4.0e-7 * 3.14159265358979323846;
+constexpr double kGM = 1.32712440018e20;
+constexpr double kPi = 3.14159265358979323846;
+
+struct Units {
+  double t, len, rho, p, b, v;
+  Units() {
+    len = kAU;
+    v = kV;
+    t = kAU / kV;
+    rho = kMp * 1.0e6;
+    p = rho * kV * kV;
+    b = std::sqrt(kMu0 * rho) * kV;
+  }
+  Scale scale() const {
+    Scale s;
+    const double c[NV] = {rho, v, v, v, p, b, b, b};
+    for (int q = 0; q < NV; ++q) s.s[q] = c[q];
+    s.t = t;
+    s.len = len;
+    return s;
+  }
+};
+
+constexpr int CHUNK = 16;  // steps per captured graph (even: parity kept)
+
+size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
+
+struct Layout {
+  size_t u[3], g[2], m64, mr, maps, tau, cme, traj, plog, pout, clock, partials, bout, total;
+  long long max_blocks;
+};
+
+Layout make_layout(const icr_grid& g, const icr_phys& p) {
+  Layout L{};
+  const size_t rs = p.precision == ICR_PREC_F32 ? 4 : 8;
+  const size_t ncell = (size_t)g.n_r * g.n_theta * g.n_phi;
+  const size_t plane = (size_t)g.n_theta * g.n_phi;
+  L.max_blocks = (long long)((g.n_r + 63) / 64) * g.n_theta * g.n_phi;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align_up(bytes);
+    return o;
+  };
+  for (int q = 0; q < 3; ++q) L.u[q] = take(NV * ncell * rs);
+  for (int q = 0; q < 2; ++q) L.g[q] = take(NV * plane * rs);
+  L.m64 = take(sizeof(double) * METRIC64_LEN(g.n_r, g.n_theta));
+  L.mr = take(rs * METRICR_LEN(g.n_r, g.n_theta));
+  L.maps = take(sizeof(double) * (size_t)g.max_maps * NV * plane);
+  L.tau = take(sizeof(double) * (size_t)g.max_maps);
+  L.cme = take(sizeof(double) * 8 * (size_t)(g.max_cmes > 0 ? g.max_cmes : 1));
+  L.traj = take(sizeof(double) * 4 * (size_t)(g.max_probes > 0 ? g.max_probes : 1) *
+                (size_t)(g.max_traj_pts > 0 ? g.max_traj_pts : 1));
+  L.plog = take(sizeof(double) * 12 * (size_t)(g.max_probes > 0 ? g.max_probes : 1) *
+                (size_t)(g.probe_log_rows > 0 ? g.probe_log_rows : 1));
+  L.pout = take(sizeof(double) * 12 * (size_t)(g.max_probes > 0 ? g.max_probes : 1));
+  L.clock = take(sizeof(DevClock));
+  L.partials = take(sizeof(double) * 4 * (size_t)L.max_blocks);
+  L.bout = take(sizeof(double) * NV * plane);
+  L.total = off;
+  return L;
+}
+
+int validate(const icr_grid* g, const icr_phys* p) {
+  if (!g || !p) return fail(ICR_ERR_ARG, "grid and phys must not be NULL");
+  if (g->n_r < 1 || g->n_theta < 1 || g->n_phi < 1)
+    return fail(ICR_ERR_ARG, "cell counts must be >= 1 (got %d %d %d)", g->n_r, g->n_theta,
+                g->n_phi);
+  const double cells = (double)g->n_r * g->n_theta * g->n_phi;
+  if (cells >= 2147483647.0) return fail(ICR_ERR_ARG, "grid too large (%.0f cells)", cells);
+  if (!(g->r_in > 0 && g->r_out > g->r_in))
+    return fail(ICR_ERR_ARG, "need 0 < r_in < r_out");
+  if (!(g->th_min > 0 && g->th_max > g->th_min && g->th_max < kPi))
+    return fail(ICR_ERR_ARG, "need 0 < th_min < th_max < pi");
+  if (g->max_maps < 1 || g->max_cmes < 0 || g->max_probes < 0 || g->max_probes > 64 ||
+      g->probe_log_rows < 0)
+    return fail(ICR_ERR_ARG, "invalid capacities (max_maps >= 1, 0 <= max_probes <= 64)");
+  if (g->max_probes > 0 && g->max_traj_pts < 2)
+    return fail(ICR_ERR_ARG, "max_traj_pts must be >= 2 when probes are used");
+  if (!(p->gamma > 1.0)) return fail(ICR_ERR_ARG, "gamma must be > 1");
+  if (!(p->cfl > 0.0 && p->cfl <= 1.0)) return fail(ICR_ERR_ARG, "cfl must be in (0, 1]");
+  if (!std::isfinite(p->omega)) return fail(ICR_ERR_ARG, "omega must be finite");
+  if (p->flux != ICR_FLUX_TVDLF && p->flux != ICR_FLUX_HLL)
+    return fail(ICR_ERR_ARG, "unknown flux %d", p->flux);
+  if (p->limiter != ICR_LIM_MINMOD && p->limiter != ICR_LIM_MC)
+    return fail(ICR_ERR_ARG, "unknown limiter %d", p->limiter);
+  if (p->precision != ICR_PREC_F64 && p->precision != ICR_PREC_F32)
+    return fail(ICR_ERR_ARG, "precision must be 64 or 32");
+  return ICR_OK;
+}
+
+}  // namespace
+
+struct icr_solver {
+  icr_grid g;
+  icr_phys p;
+  Units un;
+  bool f32;
+  hipStream_t stream;      // caller's stream: all work and graph launches
+  hipStream_t cap_stream;  // private stream used only to capture graphs
+  char* ws;
+  Layout L;
+  int cur;                 // state buffer (0/1) holding the current state
+  bool have_state, have_maps;
+  int n_maps, n_cme, n_probes, n_pts;
+  double cadence;
+  double r_in, omega, gm, dph;
+  int tile_r, variant, use_graphs;
+  hipGraphExec_t g_chunk[2], g_one[2];
+  bool graphs_ok;
+
+  void* u(int q) { return ws + L.u[q]; }
+  void* ghost(int q) { return ws + L.g[q]; }
+  double* m64() { return (double*)(ws + L.m64); }
+  void* mr() { return ws + L.mr; }
+  DevClock* clock() { return (DevClock*)(ws + L.clock); }
+  long long ncell() const { return (long long)g.n_r * g.n_theta * g.n_phi; }
+  dim3 block() const { return dim3(tile_r, 256 / tile_r); }
+  dim3 grid() const {
+    const int tt = 256 / tile_r;
+    return dim3((g.n_r + tile_r - 1) / tile_r, (g.n_theta + tt - 1) / tt, g.n_phi);
+  }
+
+  BndArgs bnd() {
+    BndArgs b;
+    b.nt = g.n_theta;
+    b.np = g.n_phi;
+    b.n_maps = n_maps;
+    b.tau = (const double*)(ws + L.tau);
+    b.maps = (const double*)(ws + L.maps);
+    b.n_cme = n_cme;
+    b.cme = (const double*)(ws + L.cme);
+    b.tc = m64() + OFF_TC64(g.n_r, g.n_theta);
+    b.dph = dph;
+    b.omega = omega;
+    b.r_in = r_in;
+    return b;
+  }
+
+  template <typename R>
+  StageArgs<R> stage_args(int uin, int un_, int uout, int gh) {
+    StageArgs<R> a;
+    a.uin = (const R*)u(uin);
+    a.un = (const R*)u(un_);
+    a.uout = (R*)u(uout);
+    a.ghost = (const R*)ghost(gh);
+    a.m = metric_view<R>((const R*)mr(), g.n_r, g.n_theta, (g.th_max - g.th_min) / g.n_theta);
+    a.clock = clock();
+    a.partials = (double*)(ws + L.partials);
+    a.nr = g.n_r;
+    a.nt = g.n_theta;
+    a.np = g.n_phi;
+    a.ncell = ncell();
+    a.gam = (R)p.gamma;
+    a.gm1 = (R)(p.gamma - 1.0);
+    a.igm1 = (R)(1.0 / (p.gamma - 1.0));
+    a.omega = (R)omega;
+    a.cfl = p.cfl;
+    a.gravity = p.gravity ? 1 : 0;
+    a.corot = p.corotation ? 1 : 0;
+    return a;
+  }
+
+  ProbeArgs probe_args() {
+    ProbeArgs a;
+    a.n = n_probes;
+    a.npts = n_pts;
+    a.max_probes = g.max_probes;
+    a.log_rows = g.probe_log_rows;
+    a.traj = (const double*)(ws + L.traj);
+    a.cadence = cadence;
+    a.sc = un.scale();
+    a.omega = omega;
+    a.gam = p.gamma;
+    a.nr = g.n_r;
+    a.nt = g.n_theta;
+    a.np = g.n_phi;
+    a.rc = m64() + 8LL * g.n_r;
+    a.tc = m64() + OFF_TC64(g.n_r, g.n_theta);
+    a.dph = dph;
+    return a;
+  }
+
+  // ev (optional): 5 events recorded around the 4 kernels of the step.
+  void enqueue_step(int from, hipStream_t st, hipEvent_t* ev = nullptr) {
+    const int to = from ^ 1;
+    if (ev) (void)hipEventRecord(ev[0], st);
+    launch_boundary(bnd(), clock(), ghost(0), ghost(1), f32, st);
+    if (ev) (void)hipEventRecord(ev[1], st);
+    if (f32) {
+      launch_stage<float>(stage_args<float>(from, from, 2, 0), 1, p.flux, p.limiter, grid(),
+                          block(), st);
+      if (ev) (void)hipEventRecord(ev[2], st);
+      launch_stage<float>(stage_args<float>(2, from, to, 1), 2, p.flux, p.limiter, grid(),
+                          block(), st);
+    } else {
+      launch_stage<double>(stage_args<double>(from, from, 2, 0), 1, p.flux, p.limiter, grid(),
+                           block(), st);
+      if (ev) (void)hipEventRecord(ev[2], st);
+      launch_stage<double>(stage_args<double>(2, from, to, 1), 2, p.flux, p.limiter, grid(),
+                           block(), st);
+    }
+    if (ev) (void)hipEventRecord(ev[3], st);
+    if (logging()) {
+      double* log = (double*)(ws + L.plog);
+      if (f32)
+        launch_probe_log<float>(probe_args(), clock(), u(to), log, st);
+      else
+        launch_probe_log<double>(probe_args(), clock(), u(to), log, st);
+    }
+    if (ev) (void)hipEventRecord(ev[4], st);
+  }
+
+  bool logging() const { return n_probes > 0 && cadence >= 0.0 && g.probe_log_rows > 0; }
+
+  void enqueue_cfl(hipStream_t st) {
+    if (f32)
+      launch_cfl<float>(stage_args<float>(cur, cur, cur, 0), grid(), block(), st);
+    else
+      launch_cfl<double>(stage_args<double>(cur, cur, cur, 0), grid(), block(), st);
+  }
+
+  void drop_graphs() {
+    if (!graphs_ok) return;
+    for (int q = 0; q < 2; ++q) {
+      (void)hipGraphExecDestroy(g_chunk[q]);
+      (void)hipGraphExecDestroy(g_one[q]);
+    }
+    graphs_ok = false;
+  }
+
+  int capture(int from, int nsteps, hipGraphExec_t* out) {
+    hipGraph_t graph;
+    HIP_TRY(hipStreamBeginCapture(cap_stream, hipStreamCaptureModeThreadLocal));
+    int f = from;
+    for (int q = 0; q < nsteps; ++q) {
+      enqueue_step(f, cap_stream);
+      f ^= 1;
+    }
+    HIP_TRY(hipStreamEndCapture(cap_stream, &graph));
+    hipError_t e = hipGraphInstantiate(out, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess)
+      return fail(ICR_ERR_HIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+    return ICR_OK;
+  }
+
+  int build_graphs() {
+    if (graphs_ok) return ICR_OK;
+    for (int q = 0; q < 2; ++q) {
+      int rc = capture(q, CHUNK, &g_chunk[q]);
+      if (rc) return rc;
+      rc = capture(q, 1, &g_one[q]);
+      if (rc) return rc;
+    }
+    graphs_ok = true;
+    return ICR_OK;
+  }
+
+  int read_clock(DevClock* h) {
+    HIP_TRY(hipMemcpyAsync(h, clock(), sizeof(DevClock), hipMemcpyDeviceToHost, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    return ICR_OK;
+  }
+  int write_clock(const DevClock* h) {
+    HIP_TRY(hipMemcpyAsync(clock(), h, sizeof(DevClock), hipMemcpyHostToDevice, stream));
+    HIP_TRY(hipStreamSynchronize(stream));
+    return ICR_OK;
+  }
+};
+
+extern "C" {
+
+const char* icr_last_error(void) { return g_err.c_str(); }
+
+int icr_units(double* out) {
+  if (!out) return fail(ICR_ERR_ARG, "out is NULL");
+  Units u;
+  out[0] = u.t;
+  out[1] = u.len;
+  out[2] = u.rho;
+  out[3] = u.p;
+  out[4] = u.b;
+  out[5] = u.v;
+  return ICR_OK;
+}
+
+int icr_workspace_bytes(const icr_grid* g, const icr_phys* p, size_t* bytes) {
+  int rc = validate(g, p);
+  if (rc) return rc;
+  if (!bytes) return fail(ICR_ERR_ARG, "bytes is NULL");
+  *bytes = make_layout(*g, *p).total;
+  return ICR_OK;
+}
+
+int icr_create(const icr_grid* g, const icr_phys* p, void* ws, size_t ws_bytes, void* stream,
+               icr_solver** out) {
+  int rc = validate(g, p);
+  if (rc) return rc;
+  if (!out) return fail(ICR_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  Layout L = make_layout(*g, *p);
+  if (!ws || ws_bytes < L.total)
+    return fail(ICR_ERR_ARG, "workspace too small: %zu < %zu bytes", ws_bytes, L.total);
+  if (((uintptr_t)ws & 255) != 0) return fail(ICR_ERR_ARG, "workspace must be 256-byte aligned");
+  icr_solver* s = new icr_solver();
+  s->g = *g;
+  s->p = *p;
+  s->f32 = p->precision == ICR_PREC_F32;
+  s->stream = (hipStream_t)stream;
+  s->ws = (char*)ws;
+  s->L = L;
+  s->cur = 0;
+  s->have_state = s->have_maps = false;
+  s->n_maps = s->n_cme = s->n_probes = s->n_pts = 0;
+  s->cadence = -1.0;
+  s->r_in = g->r_in / s->un.len;
+  s->omega = p->corotation ? p->omega * s->un.t : 0.0;
+  s->gm = p->gravity ? kGM / (s->un.len * s->un.v * s->un.v) : 0.0;
+  s->dph = 2.0 * kPi / g->n_phi;
+  s->tile_r = 64;
+  s->variant = 1;
+  s->use_graphs = 1;
+  s->graphs_ok = false;
+  hipError_t e = hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking);
+  if (e != hipSuccess) {
+    delete s;
+    return fail(ICR_ERR_HIP, "hipStreamCreate failed: %s", hipGetErrorString(e));
+  }
+  MetricArgs m;
+  m.nr = g->n_r;
+  m.nt = g->n_theta;
+  m.r_in = s->r_in;
+  m.r_out = g->r_out / s->un.len;
+  m.q = std::pow(m.r_out / m.r_in, 1.0 / g->n_r);
+  m.th_min = g->th_min;
+  m.th_max = g->th_max;
+  m.dph = s->dph;
+  m.gm = s->gm;
+  m.m64 = s->m64();
+  launch_metric(m, s->mr(), s->f32, s->stream);
+  DevClock c;
+  std::memset(&c, 0, sizeof c);
+  c.bad = BAD_NONE;
+  c.t_end = -1.0;
+  c.last_sample = -1;
+  rc = s->write_clock(&c);
+  if (rc) {
+    (void)hipStreamDestroy(s->cap_stream);
+    delete s;
+    return rc;
+  }
+  e = hipGetLastError();
+  if (e != hipSuccess) {
+    (void)hipStreamDestroy(s->cap_stream);
+    delete s;
+    return fail(ICR_ERR_HIP, "metric kernel launch failed: %s", hipGetErrorString(e));
+  }
+  *out = s;
+  return ICR_OK;
+}
+
+void icr_destroy(icr_solver* s) {
+  if (!s) return;
+  (void)hipStreamSynchronize(s->stream);
+  s->drop_graphs();
+  (void)hipStreamDestroy(s->cap_stream);
+  delete s;
+}
+
+int icr_grid_edges(const icr_solver* s, double* r, double* t, double* ph) {
+  if (!s) return fail(ICR_ERR_ARG, "solver is NULL");
+  icr_solver* m = const_cast<icr_solver*>(s);
+  const int nr = s->g.n_r, nt = s->g.n_theta, np = s->g.n_phi;
+  if (r) {
+    HIP_TRY(hipMemcpyAsync(r, m->m64() + OFF_REDGE64(nr, nt), sizeof(double) * (nr + 1),
+                           hipMemcpyDeviceToHost, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    for (int i = 0; i <= nr; ++i) r[i] *= s->un.len;
+  }
+  if (t)
+    for (int j = 0; j <= nt; ++j)
+      t[j] = s->g.th_min + (s->g.th_max - s->g.th_min) * (double)j / nt;
+  if (ph)
+    for (int k = 0; k <= np; ++k) ph[k] = 2.0 * kPi * (double)k / np;
+  return ICR_OK;
+}
+
+int icr_set_boundary_maps(icr_solver* s, int n, const double* t_s, const double* maps,
+                          int on_device) {
+  if (!s) return fail(ICR_ERR_ARG, "solver is NULL");
+  if (n < 1 || n > s->g.max_maps)
+    return fail(ICR_ERR_ARG, "n_maps = %d outside [1, %d]", n, s->g.max_maps);
+  if (!t_s || !maps) return fail(ICR_ERR_ARG, "t_s and maps must not be NULL");
+  for (int q = 1; q < n; ++q)
+    if (!(t_s[q] > t_s[q - 1])) return fail(ICR_ERR_ARG, "map times must ascend strictly");
+  const size_t plane = (size_t)s->g.n_theta * s->g.n_phi;
+  std::vector<double> h((size_t)n * NV * plane);
+  if (on_device) {
+    HIP_TRY(hipMemcpyAsync(h.data(), maps, h.size() * sizeof(double), hipMemcpyDeviceToHost,
+                           s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+  } else {
+    std::memcpy(h.data(), maps, h.size() * sizeof(double));
+  }
+  const Scale sc = s->un.scale();
+  for (int m = 0; m < n; ++m)
+    for (int v = 0; v < NV; ++v)
+      for (size_t q = 0; q < plane; ++q) {
+        double& x = h[((size_t)m * NV + v) * plane + q];
+        if ((v == 0 || v == 4) && !(x > 0.0))
+          return fail(ICR_ERR_ARG, "map %d has %s <= 0 at point %zu", m, v ? "p" : "rho", q);
+        if (!std::isfinite(x)) return fail(ICR_ERR_ARG, "map %d has a non-finite value", m);
+        x /= sc.s[v];
+      }
+  std::vector<double> tau(n);
+  for (int m = 0; m < n; ++m) tau[m] = t_s[m] / s->un.t;
+  HIP_TRY(hipMemcpyAsync(s->ws + s->L.maps, h.data(), h.size() * sizeof(double),
+                         hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipMemcpyAsync(s->ws + s->L.tau, tau.data(), n * sizeof(double), hipMemcpyHostToDevice,
+                         s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  s->n_maps = n;
+  s->have_maps = true;
+  s->drop_graphs();
+  return ICR_OK;
+}
+
+int icr_set_cmes(icr_solver* s, int n, const double* rows) {
+  if (!s) return fail(ICR_ERR_ARG, "solver is NULL");
+  if (n < 0 || n > s->g.max_cmes)
+    return fail(ICR_ERR_ARG, "n = %d outside [0, %d]", n, s->g.max_cmes);
+  if (n > 0 && !rows) return fail(ICR_ERR_ARG, "rows is NULL");
+  std::vector<double> c((size_t)8 * (n > 0 ? n : 1));
+  for (int q = 0; q < n; ++q) {
+    const double* r = rows + 8 * q;
+    if (!(r[1] > 0 && r[4] > 0 && r[5] > 0 && r[6] > 0 && r[7] > 0))
+      return fail(ICR_ERR_ARG, "CME %d: duration, half-width, speed, density, T must be > 0", q);
+    double* d = c.data() + 8 * q;
+    d[0] = r[0] / s->un.t;
+    d[1] = r[1] / s->un.t;
+    d[2] = 0.5 * kPi - r[2];
+    d[3] = r[3];
+    d[4] = std::cos(r[4]);
+    d[5] = r[5] / s->un.v;
+    d[6] = r[6] / s->un.rho;
+    d[7] = 2.0 * (r[6] / kMp) * kKb * r[7] / s->un.p;
+  }
+  if (n > 0) {
+    HIP_TRY(hipMemcpyAsync(s->ws + s->L.cme, c.data(), 8 * n * sizeof(double),
+                           hipMemcpyHostToDevice, s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+  }
+  s->n_cme = n;
+  s->drop_graphs();
+  return ICR_OK;
+}
+
+static int refresh_dt(icr_solver* s) {
+  s->enqueue_cfl(s->stream);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return ICR_OK;
+}
+
+int icr_init_radial(icr_solver* s) {
+  if (!s) return fail(ICR_ERR_ARG, "solver is NULL");
+  if (!s->have_maps) return fail(ICR_ERR_STATE, "set boundary maps first");
+  if (s->f32)
+    launch_init_radial<float>(s->bnd(), s->m64(), s->u(s->cur), s->g.n_r, s->p.gamma, s->stream);
+  else
+    launch_init_radial<double>(s->bnd(), s->m64(), s->u(s->cur), s->g.n_r, s->p.gamma,
+                               s->stream);
+  HIP_TRY(hipGetLastError());
+  DevClock c;
+  int rc = s->read_clock(&c);
+  if (rc) return rc;
+  c.t = 0.0;
+  c.step = 0;
+  c.bad = BAD_NONE;
+  c.counter = 0;
+  c.last_dt = 0.0;
+  c.resid = 0.0;
+  rc = s->write_clock(&c);
+  if (rc) return rc;
+  s->have_state = true;
+  return refresh_dt(s);
+}
+
+int icr_set_state(icr_solver* s, const double* data, int kind, int on_device) {
+  if (!s) return fail(ICR_ERR_ARG, "solver is NULL");
+  if (!data) return fail(ICR_ERR_ARG, "data is NULL");
+  if (kind != ICR_STATE_PRIM_SI && kind != ICR_STATE_CONS_CODE)
+    return fail(ICR_ERR_ARG, "unknown state kind %d", kind);
+  const long long n = s->ncell();
+  const size_t bytes = sizeof(double) * NV * (size_t)n;
+  const double* src = data;
+  double* tmp = nullptr;
+  if (!on_device) {
+    HIP_TRY(hipMalloc(&tmp, bytes));
+    hipError_t e = hipMemcpyAsync(tmp, data, bytes, hipMemcpyHostToDevice, s->stream);
+    if (e != hipSuccess) {
+      (void)hipFree(tmp);
+      return fail(ICR_ERR_HIP, "copy of the state failed: %s", hipGetErrorString(e));
+    }
+    src = tmp;
+  }
+  if (s->f32)
+    launch_import<float>(src, s->u(s->cur), n, kind, s->un.scale(), s->p.gamma, s->stream);
+  else
+    launch_import<double>(src, s->u(s->cur), n, kind, s->un.scale(), s->p.gamma, s->stream);
+  hipError_t e = hipStreamSynchronize(s->stream);
+  if (tmp) (void)hipFree(tmp);
+  if (e != hipSuccess) return fail(ICR_ERR_HIP, "state import failed: %s", hipGetErrorString(e));
+  DevClock c;
+  int rc = s->read_clock(&c);
+  if (rc) return rc;
+  c.bad = BAD_NONE;
+  c.counter = 0;
+  rc = s->write_clock(&c);
+  if (rc) return rc;
+  s->have_state = true;
+  return refresh_dt(s);
+}
+
+int icr_get_state(icr_solver* s, double* out, int kind, int on_device) {
+  if (!s) return fail(ICR_ERR_ARG, "solver is NULL");
+  if (!out) return fail(ICR_ERR_ARG, "out is NULL");
+  if (kind != ICR_STATE_PRIM_SI && kind != ICR_STATE_CONS_CODE)
+    return fail(ICR_ERR_ARG, "unknown state kind %d", kind);
+  if (!s->have_state) return fail(ICR_ERR_STATE, "no state yet");
+  const long long n = s->ncell();
+  const size_t bytes = sizeof(double) * NV * (size_t)n;
+  double* dst = out;
+  double* tmp = nullptr;
+  if (!on_device) {
+    HIP_TRY(hipMalloc(&tmp, bytes));
+    dst = tmp;
+  }
+  if (s->f32)
+    launch_export<float>(s->u(s->cur), dst, n, kind, s->un.scale(), s->p.gamma, s->stream);
+  else
+    launch_export<double>(s->u(s->cur), dst, n, kind, s->un.scale(), s->p.gamma, s->stream);
+  hipError_t e = hipSuccess;
+  if (tmp) e = hipMemcpyAsync(out, tmp, bytes, hipMemcpyDeviceToHost, s->stream);
+  hipError_t e2 = hipStreamSynchronize(s->stream);
+  if (tmp) (void)hipFree(tmp);
+  if (e != hipSuccess || e2 != hipSuccess)
+    return fail(ICR_ERR_HIP, "state export failed: %s",
+                hipGetErrorString(e != hipSuccess ? e : e2));
+  return ICR_OK;
+}
+
+int icr_get_clock(icr_solver* s, icr_clock* out) {
+  if (!s || !out) return fail(ICR_ERR_ARG, "NULL argument");
+  DevClock c;
+  int rc = s->read_clock(&c);
+  if (rc) return rc;
+  out->t = c.t * s->un.t;
+  out->step = c.step;
+  out->last_dt = c.last_dt * s->un.t;
+  out->next_dt = c.dt_cfl * s->un.t;
+  out->residual = c.resid;
+  out->t_code = c.t;
+  return ICR_OK;
+}
+
+static int set_clock_code(icr_solver* s, double tc, long long step) {
+  DevClock c;
+  int rc = s->read_clock(&c);
+  if (rc) return rc;
+  c.t = tc;
+  c.step = step;
+  if (s->cadence > 0.0) c.last_sample = (long long)std::floor(tc * s->un.t / s->cadence);
+  return s->write_clock(&c);
+}
+
+int icr_set_clock(icr_solver* s, double t, long long step) {
+  if (!s) return fail(ICR_ERR_ARG, "solver is NULL");
+  if (!std::isfinite(t) || step < 0) return fail(ICR_ERR_ARG, "invalid clock");
+  return set_clock_code(s, t / s->un.t, step);
+}
+
+int icr_set_clock_code(icr_solver* s, double t_code, long long step) {
+  if (!s) return fail(ICR_ERR_ARG, "solver is NULL");
+  if (!std::isfinite(t_code) || step < 0) return fail(ICR_ERR_ARG, "invalid clock");
+  return set_clock_code(s, t_code, step);
+}
+
+int icr_step(icr_solver* s, int n, double t_end_s, icr_step_info* info) {
+  if (!s) return fail(ICR_ERR_ARG, "solver is NULL");
+  if (n < 0) return fail(ICR_ERR_ARG, "n_steps must be >= 0");
+  if (!s->have_maps) return fail(ICR_ERR_STATE, "set boundary maps first");
+  if (!s->have_state) return fail(ICR_ERR_STATE, "initialise the state first");
+  const double tend = t_end_s > 0.0 ? t_end_s / s->un.t : -1.0;
+  launch_clock_begin(s->clock(), tend, s->stream);
+  if (s->use_graphs && n > 0) {
+    int rc = s->build_graphs();
+    if (rc) return rc;
+    int left = n;
+    while (left >= CHUNK) {
+      HIP_TRY(hipGraphLaunch(s->g_chunk[s->cur], s->stream));
+      left -= CHUNK;
+    }
+    while (left > 0) {
+      HIP_TRY(hipGraphLaunch(s->g_one[s->cur], s->stream));
+      s->cur ^= 1;
+      --left;
+    }
+  } else {
+    for (int q = 0; q < n; ++q) {
+      s->enqueue_step(s->cur, s->stream);
+      s->cur ^= 1;
+    }
+  }
+  HIP_TRY(hipGetLastError());
+  DevClock c;
+  int rc = s->read_clock(&c);
+  if (rc) return rc;
+  if (info) {
+    info->steps_taken = (int)c.taken;
+    info->status = c.bad == BAD_NONE ? ICR_OK : ICR_ERR_NONPHYSICAL;
+    info->bad_cell = c.bad == BAD_NONE ? -1 : c.bad;
+    info->t = c.t * s->un.t;
+    info->last_dt = c.last_dt * s->un.t;
+    info->residual = c.resid;
+  }
+  if (c.bad != BAD_NONE)
+    return fail(ICR_ERR_NONPHYSICAL, "non-physical cell %d after step %lld", c.bad, c.step);
+  return ICR_OK;
+}
+
+int icr_set_probes(icr_solver* s, int n, int npts, const double* traj, double cadence) {
+  if (!s) return fail(ICR_ERR_ARG, "solver is NULL");
+  if (n < 0 || n > s->g.max_probes)
+    return fail(ICR_ERR_ARG, "n = %d outside [0, %d]", n, s->g.max_probes);
+  if (n > 0) {
+    if (npts < 2 || npts > s->g.max_traj_pts)
+      return fail(ICR_ERR_ARG, "n_pts = %d outside [2, %d]", npts, s->g.max_traj_pts);
+    if (!traj) return fail(ICR_ERR_ARG, "traj is NULL");
+    if (s->g.n_r < 2 || s->g.n_theta < 2)
+      return fail(ICR_ERR_ARG, "probes need n_r >= 2 and n_theta >= 2");
+    for (int q = 0; q < n; ++q)
+      for (int m = 1; m < npts; ++m)
+        if (!(traj[((size_t)q * npts + m) * 4] > traj[((size_t)q * npts + m - 1) * 4]))
+          return fail(ICR_ERR_ARG, "trajectory %d: times must ascend strictly", q);
+    HIP_TRY(hipMemcpyAsync(s->ws + s->L.traj, traj, sizeof(double) * 4 * (size_t)n * npts,
+                           hipMemcpyHostToDevice, s->stream));
+  }
+  s->n_probes = n;
+  s->n_pts = npts;
+  s->cadence = cadence;
+  DevClock c;
+  int rc = s->read_clock(&c);
+  if (rc) return rc;
+  c.n_log = 0;
+  c.advanced = 0;
+  c.last_sample = cadence > 0.0 ? (long long)std::floor(c.t * s->un.t / cadence) : -1;
+  rc = s->write_clock(&c);
+  if (rc) return rc;
+  s->drop_graphs();
+  return ICR_OK;
+}
+
+int icr_sample_probes(icr_solver* s, double* out) {
+  if (!s || !out) return fail(ICR_ERR_ARG, "NULL argument");
+  if (!s->have_state) return fail(ICR_ERR_STATE, "no state yet");
+  if (s->n_probes == 0) return ICR_OK;
+  double* pout = (double*)(s->ws + s->L.pout);
+  if (s->f32)
+    launch_probe_sample<float>(s->probe_args(), s->clock(), s->u(s->cur), pout, s->stream);
+  else
+    launch_probe_sample<double>(s->probe_args(), s->clock(), s->u(s->cur), pout, s->stream);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(out, pout, sizeof(double) * 12 * s->n_probes, hipMemcpyDeviceToHost,
+                         s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return ICR_OK;
+}
+
+int icr_read_probe_log(icr_solver* s, double* out, int cap, int* n_rec) {
+  if (!s || !n_rec) return fail(ICR_ERR_ARG, "NULL argument");
+  if (cap > 0 && !out) return fail(ICR_ERR_ARG, "out is NULL");
+  DevClock c;
+  int rc = s->read_clock(&c);
+  if (rc) return rc;
+  *n_rec = (int)c.n_log;
+  long long rows = c.n_log;
+  if (rows > s->g.probe_log_rows) rows = s->g.probe_log_rows;
+  if (rows > cap) rows = cap;
+  if (rows > 0 && s->n_probes > 0) {
+    // log rows are [max_probes][12]; copy the first n_probes of each
+    const size_t row_b = sizeof(double) * 12 * s->g.max_probes;
+    std::vector<double> h((size_t)rows * 12 * s->g.max_probes);
+    HIP_TRY(hipMemcpyAsync(h.data(), s->ws + s->L.plog, rows * row_b, hipMemcpyDeviceToHost,
+                           s->stream));
+    HIP_TRY(hipStreamSynchronize(s->stream));
+    for (long long r = 0; r < rows; ++r)
+      std::memcpy(out + r * 12 * s->n_probes, h.data() + r * 12 * s->g.max_probes,
+                  sizeof(double) * 12 * s->n_probes);
+  }
+  return ICR_OK;
+}
+
+int icr_boundary_at(icr_solver* s, double t_s, double* out) {
+  if (!s || !out) return fail(ICR_ERR_ARG, "NULL argument");
+  if (!s->have_maps) return fail(ICR_ERR_STATE, "set boundary maps first");
+  double* d = (double*)(s->ws + s->L.bout);
+  launch_boundary_at(s->bnd(), t_s / s->un.t, d, s->un.scale(), s->stream);
+  HIP_TRY(hipGetLastError());
+  const size_t bytes = sizeof(double) * NV * s->g.n_theta * s->g.n_phi;
+  HIP_TRY(hipMemcpyAsync(out, d, bytes, hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return ICR_OK;
+}
+
+int icr_profile_steps(icr_solver* s, int n, double* avg_ms) {
+  if (!s || !avg_ms) return fail(ICR_ERR_ARG, "NULL argument");
+  if (n < 1) return fail(ICR_ERR_ARG, "n_steps must be >= 1");
+  if (!s->have_maps || !s->have_state) return fail(ICR_ERR_STATE, "maps and state first");
+  hipEvent_t ev[5];
+  for (int q = 0; q < 5; ++q) HIP_TRY(hipEventCreate(&ev[q]));
+  double acc[4] = {0, 0, 0, 0};
+  launch_clock_begin(s->clock(), -1.0, s->stream);
+  int rc = ICR_OK;
+  for (int q = 0; q < n && rc == ICR_OK; ++q) {
+    s->enqueue_step(s->cur, s->stream, ev);
+    s->cur ^= 1;
+    if (hipEventSynchronize(ev[4]) != hipSuccess) {
+      rc = fail(ICR_ERR_HIP, "event synchronisation failed");
+      break;
+    }
+    for (int k = 0; k < 4; ++k) {
+      float ms = 0.f;
+      (void)hipEventElapsedTime(&ms, ev[k], ev[k + 1]);
+      acc[k] += ms;
+    }
+  }
+  for (int q = 0; q < 5; ++q) (void)hipEventDestroy(ev[q]);
+  for (int k = 0; k < 4; ++k) avg_ms[k] = acc[k] / n;
+  if (!s->logging()) avg_ms[3] = 0.0;
+  return rc;
+}
+
+int icr_set_launch(icr_solver* s, int variant, int tile_r, int tile_t, int use_graphs) {
+  if (!s) return fail(ICR_ERR_ARG, "solver is NULL");
+  if (variant != 0 && variant != 1) return fail(ICR_ERR_ARG, "variant must be 0 or 1");
+  if (tile_r == 0) tile_r = 64;
+  if (tile_t == 0) tile_t = 256 / tile_r;
+  if (!((tile_r == 64 && tile_t == 4) || (tile_r == 128 && tile_t == 2) ||
+        (tile_r == 256 && tile_t == 1)))
+    return fail(ICR_ERR_ARG, "tile (%d, %d) not one of (64,4), (128,2), (256,1)", tile_r, tile_t);
+  s->variant = variant ? variant : 1;
+  s->tile_r = tile_r;
+  s->use_graphs = use_graphs ? 1 : 0;
+  s->drop_graphs();
+  return ICR_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,209 @@
+// icr_device.hpp -- device-side pieces of the heliospheric MHD update for
+// CDNA4 (gfx950): state conversions (Eq. 6, mu0 = 1), fast speeds, the
+// physical flux of Eqs. (1)-(4), slope limiters, the TVDLF/HLL face flux and
+// the cell-centred source terms (spherical geometry, gravity, centrifugal
+// and Coriolis force of the co-rotating frame, Sect. 2).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace icr {
+
+constexpr int NV = 8;  // rho, m_r, m_t, m_p, e, B_r, B_t, B_p
+
+enum : int { FLUX_TVDLF = 0, FLUX_HLL = 1 };
+enum : int { LIM_MINMOD = 0, LIM_MC = 1 };
+
+constexpr int BAD_NONE = 0x7fffffff;
+
+// Device-resident clock and step control.  Written by the last block of the
+// stage-2 kernel (or the CFL kernel) and by the begin-of-call kernel; read
+// by every kernel of a step so that no host round trip is needed.
+struct DevClock {
+  double t;        // current time (code units)
+  double dt;       // dt of the next step (clipped to t_end)
+  double dt_cfl;   // CFL dt of the next step before clipping
+  double t_end;    // <= 0: no end time
+  double last_dt;  // dt of the last completed step
+  double resid;    // last ||rho^{n+1} - rho^n|| / ||rho^n||
+  long long step;  // completed steps
+  long long taken; // steps completed in the current icr_step call
+  int active;      // 1: the next step advances the state
+  int clip;        // 1: the next step ends exactly at t_end
+  int bad;         // first invalid cell index or BAD_NONE
+  int advanced;    // 1: a step completed since the probe logger last ran
+  unsigned int counter;  // arrival counter of the last-block reduction
+  int pad0;
+  long long n_log;       // probe records written
+  long long last_sample; // floor(t / cadence) of the last probe record
+};
+
+// Metric factors of one precision (see k_metric for definitions).
+template <typename R>
+struct Metric {
+  const R *rm2, *rp2, *ivr, *hr, *gr, *irc, *grav, *idr, *rc;  // per r cell
+  const R *sm, *sp, *ict, *cot, *snc, *csc, *phf, *ilph;  // per theta cell
+  R ilth;                                                 // 1 / dtheta
+};
+
+template <typename R>
+__device__ __forceinline__ R rmax(R a, R b) { return a > b ? a : b; }
+template <typename R>
+__device__ __forceinline__ R rmin(R a, R b) { return a < b ? a : b; }
+
+template <typename R>
+__device__ __forceinline__ void cons2prim(const R (&u)[NV], R (&w)[NV], R gm1) {
+  const R rho = u[0];
+  const R ir = R(1) / rho;
+  w[0] = rho;
+  w[1] = u[1] * ir;
+  w[2] = u[2] * ir;
+  w[3] = u[3] * ir;
+  const R kin = R(0.5) * (u[1] * w[1] + u[2] * w[2] + u[3] * w[3]);
+  const R mag = R(0.5) * (u[5] * u[5] + u[6] * u[6] + u[7] * u[7]);
+  w[4] = gm1 * (u[4] - kin - mag);
+  w[5] = u[5];
+  w[6] = u[6];
+  w[7] = u[7];
+}
+
+template <typename R>
+__device__ __forceinline__ void prim2cons(const R (&w)[NV], R (&u)[NV], R igm1) {
+  const R rho = w[0];
+  u[0] = rho;
+  u[1] = rho * w[1];
+  u[2] = rho * w[2];
+  u[3] = rho * w[3];
+  const R kin = R(0.5) * (u[1] * w[1] + u[2] * w[2] + u[3] * w[3]);
+  const R mag = R(0.5) * (w[5] * w[5] + w[6] * w[6] + w[7] * w[7]);
+  u[4] = w[4] * igm1 + kin + mag;
+  u[5] = w[5];
+  u[6] = w[6];
+  u[7] = w[7];
+}
+
+// Fast magnetosonic speed along local component N (1..3):
+// c_f^2 = [a^2 + b^2 + sqrt((a^2 + b^2)^2 - 4 a^2 B_n^2 / rho)] / 2.
+template <typename R, int N>
+__device__ __forceinline__ R cfast(const R (&w)[NV], R gam) {
+  const R ir = R(1) / w[0];
+  const R a2 = gam * w[4] * ir;
+  const R b2 = (w[5] * w[5] + w[6] * w[6] + w[7] * w[7]) * ir;
+  const R bn = w[4 + N];
+  const R s = a2 + b2;
+  R disc = s * s - R(4) * a2 * bn * bn * ir;
+  disc = rmax(disc, R(0));
+  return sqrt(R(0.5) * (s + sqrt(disc)));
+}
+
+// Physical flux through a face normal to local component N.
+template <typename R, int N>
+__device__ __forceinline__ void phys_flux(const R (&w)[NV], const R (&u)[NV], R (&f)[NV]) {
+  const R vn = w[N], bn = w[4 + N];
+  const R ptot = w[4] + R(0.5) * (w[5] * w[5] + w[6] * w[6] + w[7] * w[7]);
+  const R vb = w[1] * w[5] + w[2] * w[6] + w[3] * w[7];
+  f[0] = w[0] * vn;
+#pragma unroll
+  for (int d = 1; d <= 3; ++d) f[d] = u[d] * vn - bn * w[4 + d];
+  f[N] += ptot;
+  f[4] = (u[4] + ptot) * vn - bn * vb;
+#pragma unroll
+  for (int d = 1; d <= 3; ++d) f[4 + d] = vn * w[4 + d] - bn * w[d];
+}
+
+template <typename R, int LIM>
+__device__ __forceinline__ R limiter(R a, R b) {
+  if (a * b <= R(0)) return R(0);
+  if (LIM == LIM_MINMOD) return fabs(a) < fabs(b) ? a : b;
+  R m = rmin(R(2) * fabs(a), R(2) * fabs(b));
+  m = rmin(m, R(0.5) * fabs(a + b));
+  return a > R(0) ? m : -m;
+}
+
+// Face states from four consecutive cells (m-2, m-1, m, m+1) around face
+// m-1/2: W_L = W_{m-1} + s_{m-1}/2, W_R = W_m - s_m/2, limited undivided
+// slopes on primitives.
+template <typename R, int LIM>
+__device__ __forceinline__ void reconstruct(const R (&a)[NV], const R (&b)[NV],
+                                            const R (&c)[NV], const R (&d)[NV],
+                                            R (&wl)[NV], R (&wr)[NV]) {
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    const R db = b[v] - a[v], dc = c[v] - b[v], dd = d[v] - c[v];
+    wl[v] = b[v] + R(0.5) * limiter<R, LIM>(db, dc);
+    wr[v] = c[v] - R(0.5) * limiter<R, LIM>(dc, dd);
+  }
+}
+
+// Numerical flux from the two face states: TVDLF
+// F = (F_L + F_R)/2 - alpha (U_R - U_L)/2, alpha = max(|v_n| + c_f), or HLL
+// with S_L = min(v_nL - c_fL, v_nR - c_fR), S_R = max(v_nL + c_fL, ...).
+template <typename R, int N, int FLUX>
+__device__ __forceinline__ void face_flux(const R (&wl)[NV], const R (&wr)[NV],
+                                          R gam, R igm1, R (&fs)[NV]) {
+  R ul[NV], ur[NV], fl[NV], fr[NV];
+  prim2cons<R>(wl, ul, igm1);
+  prim2cons<R>(wr, ur, igm1);
+  phys_flux<R, N>(wl, ul, fl);
+  phys_flux<R, N>(wr, ur, fr);
+  const R cl = cfast<R, N>(wl, gam), cr = cfast<R, N>(wr, gam);
+  if (FLUX == FLUX_TVDLF) {
+    const R alpha = rmax(fabs(wl[N]) + cl, fabs(wr[N]) + cr);
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      fs[v] = R(0.5) * (fl[v] + fr[v]) - R(0.5) * alpha * (ur[v] - ul[v]);
+  } else {
+    const R sl = rmin(wl[N] - cl, wr[N] - cr);
+    const R sr = rmax(wl[N] + cl, wr[N] + cr);
+    if (sl >= R(0)) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) fs[v] = fl[v];
+    } else if (sr <= R(0)) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) fs[v] = fr[v];
+    } else {
+      const R id = R(1) / (sr - sl);
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        fs[v] = (sr * fl[v] - sl * fr[v] + sl * sr * (ur[v] - ul[v])) * id;
+    }
+  }
+}
+
+// Cell-centred sources: spherical geometric terms with area-difference
+// pressure factors G_r = dA_r/V, H_r*cot(theta_c) = dA_theta/V; gravity
+// g = -GM/r^2 e_r (momentum rho g, energy rho v.g); co-rotating frame with
+// Omega along the polar axis: F = rho (Omega x r) x Omega + 2 rho v x Omega
+// and energy source v.F.
+template <typename R>
+__device__ __forceinline__ void add_sources(const R (&w)[NV], const Metric<R>& m, int i, int j,
+                                            R omega, int gravity, int corot, R (&L)[NV]) {
+  const R rho = w[0], vr = w[1], vt = w[2], vp = w[3], p = w[4];
+  const R br = w[5], bt = w[6], bp = w[7];
+  const R irc = m.irc[i];
+  const R cot = m.cot[j];
+  const R ptot = p + R(0.5) * (br * br + bt * bt + bp * bp);
+  L[1] += (rho * (vt * vt + vp * vp) - (bt * bt + bp * bp)) * irc + ptot * m.gr[i];
+  L[2] += (-(rho * vr * vt - br * bt) + cot * (rho * vp * vp - bp * bp)) * irc +
+          ptot * m.hr[i] * cot;
+  L[3] -= ((rho * vp * vr - bp * br) + cot * (rho * vp * vt - bp * bt)) * irc;
+  L[6] += (vr * bt - vt * br) * irc;
+  L[7] += ((vr * bp - vp * br) + cot * (vt * bp - vp * bt)) * irc;
+  if (gravity) {
+    const R g = m.grav[i];
+    L[1] += rho * g;
+    L[4] += rho * vr * g;
+  }
+  if (corot) {
+    const R sn = m.snc[j], cs = m.csc[j];
+    const R r = m.rc[i];
+    const R cen = rho * omega * omega * r * sn;
+    const R cor = R(2) * rho * omega;
+    L[1] += cen * sn + cor * vp * sn;
+    L[2] += cen * cs + cor * vp * cs;
+    L[3] -= cor * (vr * sn + vt * cs);
+    L[4] += cen * (vr * sn + vt * cs);
+  }
+}
+
+}  // namespace icr

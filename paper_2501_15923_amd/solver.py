@@ -1,0 +1,156 @@
+"""Thin Python binding over the C-ABI (include/icarus_hip.h).
+
+PyTorch provides the device workspace and the stream; every step of the
+update runs in the HIP kernels of libicarus_hip.so.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _abi
+from ._abi import check, lib
+from .synth import AU, DEG, Grid, OMEGA_SUN
+
+
+def _np_ptr(a: np.ndarray):
+    return a.ctypes.data_as(_abi.D)
+
+
+class Solver:
+    def __init__(self, grid: Grid, *, gamma=1.5, omega=OMEGA_SUN, cfl=0.4,
+                 flux=_abi.FLUX_TVDLF, limiter=_abi.LIM_MINMOD, precision=64,
+                 gravity=True, corotation=True, max_maps=16, max_cmes=4, max_probes=8,
+                 max_traj_pts=1024, probe_log_rows=0, device=0, stream=None):
+        import torch
+        self.torch = torch
+        self.grid = grid
+        self.device = torch.device("cuda", device)
+        self.g = _abi.IcrGrid(grid.nr, grid.nt, grid.np_, grid.r_in, grid.r_out, grid.th_min,
+                              grid.th_max, max_maps, max_cmes, max_probes, max_traj_pts,
+                              probe_log_rows)
+        self.p = _abi.IcrPhys(gamma, omega, cfl, flux, limiter, precision, int(gravity),
+                              int(corotation))
+        nbytes = ctypes.c_size_t()
+        check(lib().icr_workspace_bytes(ctypes.byref(self.g), ctypes.byref(self.p),
+                                        ctypes.byref(nbytes)))
+        self.ws_bytes = nbytes.value
+        self._ws = torch.empty(self.ws_bytes + 256, dtype=torch.uint8, device=self.device)
+        base = self._ws.data_ptr()
+        self.ws_ptr = (base + 255) & ~255
+        if stream is None:
+            stream = torch.cuda.current_stream(self.device)
+        self.stream = stream
+        h = ctypes.c_void_p()
+        with torch.cuda.device(self.device):
+            check(lib().icr_create(ctypes.byref(self.g), ctypes.byref(self.p),
+                                   ctypes.c_void_p(self.ws_ptr), self.ws_bytes,
+                                   ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)))
+        self.h = h
+        self.n_probes = 0
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().icr_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def shape(self):
+        return (8, self.grid.np_, self.grid.nt, self.grid.nr)
+
+    # ---- setup -----------------------------------------------------------
+    def edges(self):
+        r = np.zeros(self.grid.nr + 1)
+        t = np.zeros(self.grid.nt + 1)
+        p = np.zeros(self.grid.np_ + 1)
+        check(lib().icr_grid_edges(self.h, _np_ptr(r), _np_ptr(t), _np_ptr(p)))
+        return r, t, p
+
+    def set_maps(self, times, maps):
+        times = np.ascontiguousarray(times, dtype=np.float64)
+        maps = np.ascontiguousarray(maps, dtype=np.float64)
+        check(lib().icr_set_boundary_maps(self.h, len(times), _np_ptr(times), _np_ptr(maps), 0))
+
+    def set_cmes(self, rows):
+        rows = np.ascontiguousarray(np.atleast_2d(rows), dtype=np.float64)
+        n = 0 if rows.size == 0 else rows.shape[0]
+        check(lib().icr_set_cmes(self.h, n, _np_ptr(rows) if n else None))
+
+    def init_radial(self):
+        check(lib().icr_init_radial(self.h))
+
+    def set_state(self, a, kind=_abi.STATE_PRIM_SI):
+        if hasattr(a, "data_ptr"):
+            check(lib().icr_set_state(self.h, _abi.dptr(a.data_ptr()), kind, 1))
+        else:
+            a = np.ascontiguousarray(a, dtype=np.float64)
+            check(lib().icr_set_state(self.h, _np_ptr(a), kind, 0))
+
+    def get_state(self, kind=_abi.STATE_PRIM_SI):
+        out = np.zeros(self.shape)
+        check(lib().icr_get_state(self.h, _np_ptr(out), kind, 0))
+        return out
+
+    def clock(self):
+        c = _abi.IcrClock()
+        check(lib().icr_get_clock(self.h, ctypes.byref(c)))
+        return dict(t=c.t, step=c.step, last_dt=c.last_dt, next_dt=c.next_dt,
+                    resid=c.residual, t_code=c.t_code)
+
+    def set_clock(self, t, step=0):
+        check(lib().icr_set_clock(self.h, float(t), int(step)))
+
+    def set_clock_code(self, t_code, step=0):
+        check(lib().icr_set_clock_code(self.h, float(t_code), int(step)))
+
+    def step(self, n, t_end=-1.0, raise_on_error=True):
+        info = _abi.IcrStepInfo()
+        rc = lib().icr_step(self.h, int(n), float(t_end), ctypes.byref(info))
+        if raise_on_error:
+            check(rc)
+        return dict(rc=rc, steps=info.steps_taken, status=info.status, bad_cell=info.bad_cell,
+                    t=info.t, dt=info.last_dt, resid=info.residual)
+
+    def set_probes(self, traj, cadence=-1.0):
+        traj = np.ascontiguousarray(traj, dtype=np.float64)
+        self.n_probes = traj.shape[0]
+        check(lib().icr_set_probes(self.h, traj.shape[0], traj.shape[1], _np_ptr(traj),
+                                   float(cadence)))
+
+    def sample_probes(self):
+        out = np.zeros((self.n_probes, 12))
+        check(lib().icr_sample_probes(self.h, _np_ptr(out)))
+        return out
+
+    def read_probe_log(self, cap=100000):
+        out = np.zeros((cap, self.n_probes, 12))
+        n = ctypes.c_int()
+        check(lib().icr_read_probe_log(self.h, _np_ptr(out), cap, ctypes.byref(n)))
+        return out[:min(n.value, cap)], n.value
+
+    def boundary_at(self, t):
+        out = np.zeros((8, self.grid.nt, self.grid.np_))
+        check(lib().icr_boundary_at(self.h, float(t), _np_ptr(out)))
+        return out
+
+    def set_launch(self, variant=0, tile_r=0, tile_t=0, use_graphs=1):
+        check(lib().icr_set_launch(self.h, variant, tile_r, tile_t, use_graphs))
+
+    def profile_steps(self, n):
+        """Mean ms per launch of (boundary, stage 1, stage 2, probe logger)."""
+        out = np.zeros(4)
+        check(lib().icr_profile_steps(self.h, int(n), _np_ptr(out)))
+        return out
+
+
+def units() -> dict:
+    out = np.zeros(6)
+    check(lib().icr_units(_np_ptr(out)))
+    return dict(t=out[0], L=out[1], rho=out[2], p=out[3], B=out[4], v=out[5])

@@ -1,0 +1,87 @@
+"""CPU checks of the C-ABI library: it loads, exports every function that
+include/icarus_hip.h declares, and validates arguments on the host (no GPU
+call is made by icr_workspace_bytes)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "icarus_hip.h")
+
+
+def declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(icr_[a-z_0-9]+)\s*\(", txt)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_2501_15923_amd import _abi
+    return _abi
+
+
+def test_header_declares_the_boundary():
+    names = declared()
+    for must in ("icr_create", "icr_set_boundary_maps", "icr_step", "icr_sample_probes",
+                 "icr_workspace_bytes", "icr_grid_edges"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol(lib):
+    L = lib.lib()
+    for name in declared():
+        assert hasattr(L, name), name
+    assert set(declared()) == set(lib.SIGNATURES), "binding and header disagree"
+
+
+def _grid(lib, **kw):
+    from paper_2501_15923_amd import synth
+    d = dict(n_r=600, n_theta=60, n_phi=120, r_in=0.1 * synth.AU, r_out=2 * synth.AU,
+             th_min=30 * synth.DEG, th_max=150 * synth.DEG, max_maps=10, max_cmes=1,
+             max_probes=4, max_traj_pts=500, probe_log_rows=100)
+    d.update(kw)
+    return lib.IcrGrid(**d)
+
+
+def _phys(lib, **kw):
+    d = dict(gamma=1.5, omega=2.87e-6, cfl=0.4, flux=0, limiter=0, precision=64, gravity=1,
+             corotation=1)
+    d.update(kw)
+    return lib.IcrPhys(**d)
+
+
+def test_workspace_size_and_validation(lib):
+    L = lib.lib()
+    n = ctypes.c_size_t()
+    g, p = _grid(lib), _phys(lib)
+    assert L.icr_workspace_bytes(ctypes.byref(g), ctypes.byref(p), ctypes.byref(n)) == 0
+    state = 8 * 600 * 60 * 120 * 8
+    assert 3 * state < n.value < 3 * state * 1.05
+    p32 = _phys(lib, precision=32)
+    n32 = ctypes.c_size_t()
+    assert L.icr_workspace_bytes(ctypes.byref(g), ctypes.byref(p32), ctypes.byref(n32)) == 0
+    assert n32.value < 0.6 * n.value
+    bad = [
+        (_grid(lib, n_r=0), p), (_grid(lib, r_out=0.05 * 1.5e11), p),
+        (_grid(lib, th_min=0.0), p), (_grid(lib, th_max=3.5), p),
+        (_grid(lib, n_r=2000, n_theta=2000, n_phi=1000), p),  # > 2^31 cells
+        (_grid(lib, max_maps=0), p), (_grid(lib, max_probes=2, max_traj_pts=1), p),
+        (g, _phys(lib, gamma=1.0)), (g, _phys(lib, cfl=0.0)), (g, _phys(lib, cfl=1.5)),
+        (g, _phys(lib, flux=7)), (g, _phys(lib, limiter=3)), (g, _phys(lib, precision=16)),
+    ]
+    for gg, pp in bad:
+        rc = L.icr_workspace_bytes(ctypes.byref(gg), ctypes.byref(pp), ctypes.byref(n))
+        assert rc == lib.ICR_ERR_ARG
+        assert len(L.icr_last_error()) > 0
+
+
+def test_units_match_the_oracle(lib):
+    import numpy as np
+    import oracle
+    out = np.zeros(6)
+    assert lib.lib().icr_units(out.ctypes.data_as(lib.D)) == 0
+    u = oracle.units()
+    assert np.allclose(out, [u["t"], u["L"], u["rho"], u["p"], u["B"], u["v"]], rtol=1e-15)

@@ -1,0 +1,289 @@
+"""Parity of the HIP path (through the C-ABI) with the CPU oracle.
+
+FP64 bar: max relative error per conserved-variable group <= 1e-9 (see
+parity.py).  Sizes: the tiny static workload (64 x 16 x 32) for 100 and 200
+steps; a ragged 150 x 30 x 60 grid (not a multiple of the 64 x 4 tile) with
+time-interpolated maps and an active cone CME; degenerate 1D/2D grids; and
+the production grid 600 x 60 x 120 for a few steps in the launch
+configuration the bench uses.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+import parity
+from paper_2501_15923_amd import configs, synth
+
+pytestmark = pytest.mark.gpu
+
+AU = synth.AU
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mods():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import oracle
+    from paper_2501_15923_amd import _abi, solver
+    _abi.lib()  # fails loudly when the HIP library is missing
+    return oracle, solver, _abi
+
+
+def pair(mods, grid, times, maps, cmes=None, *, flux=0, limiter=0, gravity=True, corot=True,
+         omega=synth.OMEGA_SUN, gamma=1.5, cfl=0.4, precision=64, **kw):
+    oracle, solver, _ = mods
+    s = solver.Solver(grid, flux=flux, limiter=limiter, gravity=gravity, corotation=corot,
+                      omega=omega, gamma=gamma, cfl=cfl, precision=precision, **kw)
+    o = oracle.Oracle(grid.nr, grid.nt, grid.np_, flux=flux, limiter=limiter, gravity=gravity,
+                      corot=corot, omega=omega, gamma=gamma, cfl=cfl,
+                      r_in=grid.r_in, r_out=grid.r_out, th_min=grid.th_min,
+                      th_max=grid.th_max)
+    s.set_maps(times, maps)
+    o.set_maps(times, maps)
+    if cmes is not None:
+        s.set_cmes(cmes)
+        o.set_cmes(cmes)
+    s.init_radial()
+    o.init_radial()
+    return s, o
+
+
+def cons(mods, s, o):
+    oracle = mods[0]
+    return s.get_state(kind=1), o.get_state(kind=oracle.CONS_CODE)
+
+
+def test_grid_edges_match_oracle(mods):
+    g = synth.Grid(150, 30, 60)
+    w = configs.tiny_static()
+    s, o = pair(mods, g, np.zeros(1), synth.static_map(g, 0)[None])
+    r, t, p = s.edges()
+    ro, to, po = o.edges()
+    assert np.max(np.abs(r / (ro * AU) - 1)) < 1e-14
+    assert np.max(np.abs(t - to)) < 1e-15
+    assert np.max(np.abs(p - po)) < 1e-14
+    del w
+
+
+def test_boundary_driver_matches_oracle(mods):
+    g = synth.Grid(32, 30, 60)
+    times, maps = synth.dynamic_maps(g, 7, cadence=3600.0)
+    cme = np.array([1800.0, 7200.0, 5 * synth.DEG, 1.0, 30 * synth.DEG, 1.0e6, 1e-18, 0.8e6])
+    s, o = pair(mods, g, times, maps, cme[None])
+    for t in (-10.0, 0.0, 1000.0, 1800.0, 3600.0, 5000.5, 9000.0, 9000.0 + 1e-3, 3.3e4, 1e6):
+        a, b = s.boundary_at(t), o.inner_boundary(t)
+        scale = np.max(np.abs(b), axis=(1, 2), keepdims=True)
+        scale[scale == 0] = 1.0
+        err = np.max(np.abs(a - b) / scale)
+        assert err < 1e-14, (t, err)
+
+
+def test_init_and_dt_match_oracle(mods):
+    w = configs.tiny_static()
+    s, o = pair(mods, w.grid, w.times, w.maps)
+    a, b = cons(mods, s, o)
+    assert parity.max_rel(a, b) < 1e-14
+    assert abs(s.clock()["next_dt"] / o.dt() - 1) < 1e-13
+
+
+@pytest.mark.parametrize("steps", [100, 200])
+def test_tiny_static_parity(mods, steps):
+    w = configs.tiny_static()
+    s, o = pair(mods, w.grid, w.times, w.maps)
+    say(f"tiny static {w.grid}, {steps} steps")
+    info = s.step(steps)
+    o.step(steps)
+    assert info["steps"] == steps
+    a, b = cons(mods, s, o)
+    e = parity.assert_parity(a, b, what=f"tiny static {steps} steps")
+    say("errors", e)
+    assert abs(s.clock()["t"] / o.clock()["t"] - 1) < 1e-11
+
+
+@pytest.mark.parametrize("flux,limiter", [(1, 0), (0, 1), (1, 1)])
+def test_scheme_variants_parity(mods, flux, limiter):
+    w = configs.tiny_static()
+    s, o = pair(mods, w.grid, w.times, w.maps, flux=flux, limiter=limiter)
+    say(f"variant flux={flux} limiter={limiter}")
+    s.step(60)
+    o.step(60)
+    parity.assert_parity(*cons(mods, s, o), what=f"flux={flux} lim={limiter}")
+
+
+def test_ragged_dynamic_cme_parity(mods):
+    g = synth.Grid(150, 30, 60)
+    times, maps = synth.dynamic_maps(g, 11, cadence=1800.0)
+    earth = synth.orbit_table(2 * synth.DAY, 600.0, AU)
+    cme = synth.cone_cme(12, earth, t_start=600.0, duration=4 * 3600.0)
+    s, o = pair(mods, g, times, maps, cme[None])
+    say("ragged 150x30x60 dynamic + CME, 25 steps")
+    s.step(25)
+    o.step(25)
+    parity.assert_parity(*cons(mods, s, o), what="ragged dynamic cme")
+    assert abs(s.clock()["t"] / o.clock()["t"] - 1) < 1e-11
+
+
+def test_options_parity(mods):
+    g = synth.Grid(40, 12, 20)
+    times, maps = synth.dynamic_maps(g, 13, cadence=3600.0)
+    for grav, corot in ((False, False), (True, False), (False, True)):
+        s, o = pair(mods, g, times, maps, gravity=grav, corot=corot)
+        s.step(40)
+        o.step(40)
+        parity.assert_parity(*cons(mods, s, o), what=f"gravity={grav} corot={corot}")
+
+
+@pytest.mark.parametrize("shape", [(3, 1, 1), (5, 1, 7), (9, 3, 1), (70, 2, 3)])
+def test_degenerate_grids_parity(mods, shape):
+    g = synth.Grid(*shape)
+    m = synth.static_map(g, 1)
+    s, o = pair(mods, g, np.zeros(1), m[None])
+    s.step(30)
+    o.step(30)
+    parity.assert_parity(*cons(mods, s, o), what=f"grid {shape}")
+
+
+def test_zero_steps_and_t_end(mods):
+    w = configs.tiny_static()
+    s, o = pair(mods, w.grid, w.times, w.maps)
+    a0 = s.get_state(kind=1)
+    info = s.step(0)
+    assert info["steps"] == 0
+    assert np.array_equal(a0, s.get_state(kind=1))
+    t_end = 2000.0
+    info = s.step(100, t_end=t_end)
+    oi = o.step(100, t_end=t_end)
+    assert info["steps"] == oi["steps"]
+    assert s.clock()["t"] == pytest.approx(t_end, rel=1e-15)
+    before = s.get_state(kind=1)
+    info = s.step(5, t_end=t_end)
+    assert info["steps"] == 0
+    assert np.array_equal(before, s.get_state(kind=1))
+    parity.assert_parity(before, o.get_state(kind=mods[0].CONS_CODE), what="t_end")
+
+
+def test_tiling_graphs_and_determinism_bitwise(mods):
+    g = synth.Grid(150, 30, 20)
+    times, maps = synth.dynamic_maps(g, 3, cadence=3600.0)
+    ref = None
+    for tile_r, graphs in ((64, 1), (128, 1), (256, 1), (64, 0), (64, 1)):
+        s, _ = pair(mods, g, times, maps)
+        s.set_launch(0, tile_r, 0, graphs)
+        s.step(23)
+        a = s.get_state(kind=1)
+        if ref is None:
+            ref = a
+        else:
+            assert np.array_equal(ref, a), (tile_r, graphs)
+
+
+def test_restart_is_bitwise(mods):
+    g = synth.Grid(64, 16, 32)
+    times, maps = synth.dynamic_maps(g, 4, cadence=3600.0)
+    s, _ = pair(mods, g, times, maps)
+    s.step(37)
+    full = s.get_state(kind=1)
+    s2, _ = pair(mods, g, times, maps)
+    s2.step(20)
+    U = s2.get_state(kind=1)
+    c = s2.clock()
+    s3, _ = pair(mods, g, times, maps)
+    s3.set_state(U, kind=1)
+    s3.set_clock_code(c["t_code"], c["step"])
+    s3.step(17)
+    assert np.array_equal(full, s3.get_state(kind=1))
+    assert s3.clock()["step"] == 37
+
+
+def test_nonphysical_state_is_flagged(mods):
+    w = configs.tiny_static()
+    s, o = pair(mods, w.grid, w.times, w.maps)
+    W = s.get_state()
+    W[4, 5, 7, 40] = -1e-9
+    s.set_state(W)
+    o.set_state(W)
+    info = s.step(3, raise_on_error=False)
+    oi = o.step(3)
+    assert info["rc"] == -3 and info["status"] == -3
+    assert oi["status"] == -3
+    assert info["bad_cell"] == oi["bad_cell"]
+    assert info["steps"] == oi["steps"] == 1
+
+
+def test_fp32_mode_error_vs_fp64(mods):
+    w = configs.tiny_static()
+    s64, _ = pair(mods, w.grid, w.times, w.maps)
+    s32, _ = pair(mods, w.grid, w.times, w.maps, precision=32)
+    s64.step(100)
+    s32.step(100)
+    e = parity.rel_errors(s32.get_state(kind=1), s64.get_state(kind=1))
+    say("fp32 vs fp64 after 100 steps:", e)
+    assert max(e.values()) < 1e-3
+
+
+def _probe_tables(t_end):
+    tabs = synth.probe_tables(t_end, 5, cadence=600.0)
+    return tabs
+
+
+def test_probe_sampling_parity(mods):
+    w = configs.tiny_static()
+    s, o = pair(mods, w.grid, w.times, w.maps)
+    tabs = _probe_tables(2 * synth.DAY)
+    s.set_probes(tabs, cadence=-1.0)
+    s.step(50)
+    o.step(50)
+    a = s.sample_probes()
+    b = o.sample(tabs)
+    assert np.allclose(a[:, :4], b[:, :4], rtol=1e-12, atol=1e-9)
+    for v in range(4, 12):
+        scale = np.max(np.abs(b[:, v])) + 1e-300
+        assert np.max(np.abs(a[:, v] - b[:, v])) / scale < 1e-9, v
+
+
+def test_probe_log_cadence_parity(mods):
+    w = configs.tiny_static()
+    s, o = pair(mods, w.grid, w.times, w.maps, probe_log_rows=64)
+    tabs = _probe_tables(2 * synth.DAY)
+    cad = 1000.0
+    s.set_probes(tabs, cadence=cad)
+    s.step(40)
+    log, n = s.read_probe_log()
+    rows = []
+    last = math.floor(0.0 / cad)
+    for _ in range(40):
+        o.step(1)
+        t = o.clock()["t"]
+        if math.floor(t / cad) > last:
+            last = math.floor(t / cad)
+            rows.append(o.sample(tabs))
+    assert n == len(rows) > 3
+    for a, b in zip(log, rows):
+        assert a[0, 0] == pytest.approx(b[0, 0], rel=1e-12)
+        for v in range(4, 12):
+            scale = np.max(np.abs(b[:, v])) + 1e-300
+            assert np.max(np.abs(a[:, v] - b[:, v])) / scale < 1e-9
+
+
+@pytest.mark.parametrize("what", ["dynamic", "cme"])
+def test_production_grid_parity(mods, what):
+    """600 x 60 x 120 in the bench's launch configuration, a few steps."""
+    w = configs.prod_dynamic() if what == "dynamic" else configs.prod_cme()
+    s, o = pair(mods, w.grid, w.times, w.maps, w.cmes if len(w.cmes) else None)
+    if what == "cme":
+        # start inside the CME insertion window and mid-way between maps
+        t0 = w.cmes[0][0] + 600.0
+        s.set_clock(t0)
+        o.set_clock(t0)
+    say(f"production grid {what}: 3 steps")
+    s.step(3)
+    o.step(3)
+    e = parity.assert_parity(*cons(mods, s, o), what=f"production {what}")
+    say("errors", e)
