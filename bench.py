@@ -44,7 +44,22 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--traffic", default=os.path.join(ROOT, "profiles", "stage2_traffic.json"),
                     help="HBM traffic per stage-2 launch measured with rocprofv3 counters")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a device-to-device copy of known size (counter calibration)")
     return ap.parse_args()
+
+
+def copy_calibration():
+    """A plain device copy of 2 GiB, three times: the reference that scales
+    the FETCH_SIZE / WRITE_SIZE counters to bytes."""
+    import torch
+    n = 1 << 28  # doubles = 2 GiB
+    a = torch.ones(n, dtype=torch.float64, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_bytes": 8 * n, "launches": 3}), flush=True)
 
 
 def cpu_baseline(w, steps):
@@ -69,6 +84,9 @@ def cpu_baseline(w, steps):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration()
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
               "sharding of this path is a design note, not a measured configuration.",
@@ -144,7 +162,7 @@ def kernel_rev():
     """Identifies the stage-kernel source the traffic counters were taken on."""
     import hashlib
     h = hashlib.sha1()
-    for f in ("icr_kernels.hip", "icr_device.hpp"):
+    for f in ("icr_kernels.hip", "icr_stage_lds.hip", "icr_device.hpp", "icr_kernels.hpp"):
         h.update(open(os.path.join(ROOT, "paper_2501_15923_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:12]
 

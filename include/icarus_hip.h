@@ -221,18 +221,21 @@ int icr_read_probe_log(icr_solver *s, double *out, int cap, int *n_rec);
  * time interpolation and the CME overwrite: out [8][n_theta][n_phi] host. */
 int icr_boundary_at(icr_solver *s, double t_s, double *out);
 
-/* Launch configuration of the fused stage kernel: variant 0 = default,
- * 1 = one thread per cell with on-the-fly neighbour primitives; tile
- * (tile_r, tile_t) in {(64, 4), (128, 2), (256, 1)} (0 = default);
- * use_graphs 0/1 replays steps from captured HIP graphs.  Every variant
- * and tile gives bit-identical results. */
-int icr_set_launch(icr_solver *s, int variant, int tile_r, int tile_t,
+/* Launch configuration of the fused stage kernels.  variant: 0 = default
+ * (2), 1 = one thread per cell with on-the-fly neighbour primitives, 2 =
+ * face-once kernel (LDS tile with halo in r/theta, registers along phi).
+ * tile_r: lanes along r per block (variant 1: 64, 128, 256; variant 2: 32,
+ * 64; 0 = 64); 256 threads per block.  planes: phi planes per block of
+ * variant 2 (1..n_phi, 0 = 8).  use_graphs: 1 replays steps from captured
+ * HIP graphs.  All tiles and plane counts of one variant give bit-identical
+ * results; the two variants agree to rounding. */
+int icr_set_launch(icr_solver *s, int variant, int tile_r, int planes,
                    int use_graphs);
 
 /* Advance n_steps (> 0) steps with direct launches, timing each kernel with
  * HIP events on the solver's stream.  avg_ms[4] receives the mean duration
- * of the boundary driver, stage 1, stage 2 and the probe logger (0 if not
- * launched).  Same results as icr_step. */
+ * of the boundary driver, stage 1, stage 2 and the finalize kernel (clock,
+ * dt and probe record).  Same results as icr_step. */
 int icr_profile_steps(icr_solver *s, int n_steps, double *avg_ms);
 
 #ifdef __cplusplus

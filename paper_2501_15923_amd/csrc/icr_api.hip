@@ -82,7 +82,18 @@ Layout make_layout(const icr_grid& g, const icr_phys& p) {
   const size_t rs = p.precision == ICR_PREC_F32 ? 4 : 8;
   const size_t ncell = (size_t)g.n_r * g.n_theta * g.n_phi;
   const size_t plane = (size_t)g.n_theta * g.n_phi;
-  L.max_blocks = (long long)((g.n_r + 63) / 64) * g.n_theta * g.n_phi;
+  // partial slots: the largest grid of any stage-kernel launch configuration
+  long long mb = 0;
+  for (int tr : {64, 128, 256}) {
+    const long long b = (long long)((g.n_r + tr - 1) / tr) *
+                        ((g.n_theta + 256 / tr - 1) / (256 / tr)) * g.n_phi;
+    mb = b > mb ? b : mb;
+  }
+  for (int tr : {32, 64}) {
+    const long long b = stage_lds_blocks(g.n_r, g.n_theta, g.n_phi, tr, 1);
+    mb = b > mb ? b : mb;
+  }
+  L.max_blocks = mb;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -152,7 +163,7 @@ struct icr_solver {
   int n_maps, n_cme, n_probes, n_pts;
   double cadence;
   double r_in, omega, gm, dph;
-  int tile_r, variant, use_graphs;
+  int tile_r, variant, use_graphs, planes;
   hipGraphExec_t g_chunk[2], g_one[2];
   bool graphs_ok;
 
@@ -162,10 +173,19 @@ struct icr_solver {
   void* mr() { return ws + L.mr; }
   DevClock* clock() { return (DevClock*)(ws + L.clock); }
   long long ncell() const { return (long long)g.n_r * g.n_theta * g.n_phi; }
-  dim3 block() const { return dim3(tile_r, 256 / tile_r); }
+  // thread-per-cell launches (variant 1 and the CFL kernel)
+  int v1_tile() const { return variant == 1 ? tile_r : 64; }
+  dim3 block() const { return dim3(v1_tile(), 256 / v1_tile()); }
   dim3 grid() const {
-    const int tt = 256 / tile_r;
-    return dim3((g.n_r + tile_r - 1) / tile_r, (g.n_theta + tt - 1) / tt, g.n_phi);
+    const int tr = v1_tile(), tt = 256 / tr;
+    return dim3((g.n_r + tr - 1) / tr, (g.n_theta + tt - 1) / tt, g.n_phi);
+  }
+  int stage_blocks() const {
+    if (variant == 1) {
+      const dim3 gr = grid();
+      return (int)(gr.x * gr.y * gr.z);
+    }
+    return (int)stage_lds_blocks(g.n_r, g.n_theta, g.n_phi, tile_r, planes);
   }
 
   BndArgs bnd() {
@@ -228,43 +248,52 @@ struct icr_solver {
     return a;
   }
 
-  // ev (optional): 5 events recorded around the 4 kernels of the step.
+  template <typename R>
+  void enqueue_stages(int from, int to, hipStream_t st, hipEvent_t* ev) {
+    const StageArgs<R> a1 = stage_args<R>(from, from, 2, 0);
+    const StageArgs<R> a2 = stage_args<R>(2, from, to, 1);
+    if (variant == 1) {
+      launch_stage<R>(a1, 1, p.flux, p.limiter, grid(), block(), st);
+      if (ev) (void)hipEventRecord(ev[2], st);
+      launch_stage<R>(a2, 2, p.flux, p.limiter, grid(), block(), st);
+    } else {
+      launch_stage_lds<R>(a1, 1, p.flux, p.limiter, tile_r, planes, st);
+      if (ev) (void)hipEventRecord(ev[2], st);
+      launch_stage_lds<R>(a2, 2, p.flux, p.limiter, tile_r, planes, st);
+    }
+    if (ev) (void)hipEventRecord(ev[3], st);
+    launch_finalize<R>(clock(), (const double*)(ws + L.partials), stage_blocks(), p.cfl, 1,
+                       logging() ? 1 : 0, probe_args(), u(to), (double*)(ws + L.plog), st);
+  }
+
+  // One RK2 step from state buffer `from` into `from ^ 1`: boundary driver,
+  // stage 1, stage 2, finalize (clock, dt, probe record).  ev (optional):
+  // 5 events around the four kernels.
   void enqueue_step(int from, hipStream_t st, hipEvent_t* ev = nullptr) {
     const int to = from ^ 1;
     if (ev) (void)hipEventRecord(ev[0], st);
     launch_boundary(bnd(), clock(), ghost(0), ghost(1), f32, st);
     if (ev) (void)hipEventRecord(ev[1], st);
-    if (f32) {
-      launch_stage<float>(stage_args<float>(from, from, 2, 0), 1, p.flux, p.limiter, grid(),
-                          block(), st);
-      if (ev) (void)hipEventRecord(ev[2], st);
-      launch_stage<float>(stage_args<float>(2, from, to, 1), 2, p.flux, p.limiter, grid(),
-                          block(), st);
-    } else {
-      launch_stage<double>(stage_args<double>(from, from, 2, 0), 1, p.flux, p.limiter, grid(),
-                           block(), st);
-      if (ev) (void)hipEventRecord(ev[2], st);
-      launch_stage<double>(stage_args<double>(2, from, to, 1), 2, p.flux, p.limiter, grid(),
-                           block(), st);
-    }
-    if (ev) (void)hipEventRecord(ev[3], st);
-    if (logging()) {
-      double* log = (double*)(ws + L.plog);
-      if (f32)
-        launch_probe_log<float>(probe_args(), clock(), u(to), log, st);
-      else
-        launch_probe_log<double>(probe_args(), clock(), u(to), log, st);
-    }
+    if (f32)
+      enqueue_stages<float>(from, to, st, ev);
+    else
+      enqueue_stages<double>(from, to, st, ev);
     if (ev) (void)hipEventRecord(ev[4], st);
   }
 
   bool logging() const { return n_probes > 0 && cadence >= 0.0 && g.probe_log_rows > 0; }
 
   void enqueue_cfl(hipStream_t st) {
-    if (f32)
-      launch_cfl<float>(stage_args<float>(cur, cur, cur, 0), grid(), block(), st);
-    else
-      launch_cfl<double>(stage_args<double>(cur, cur, cur, 0), grid(), block(), st);
+    const dim3 gr(((unsigned)g.n_r + 63) / 64, ((unsigned)g.n_theta + 3) / 4, g.n_phi);
+    const int nb = (int)(gr.x * gr.y * gr.z);
+    const double* part = (const double*)(ws + L.partials);
+    if (f32) {
+      launch_cfl<float>(stage_args<float>(cur, cur, cur, 0), gr, dim3(64, 4), st);
+      launch_finalize<float>(clock(), part, nb, p.cfl, 0, 0, probe_args(), u(cur), nullptr, st);
+    } else {
+      launch_cfl<double>(stage_args<double>(cur, cur, cur, 0), gr, dim3(64, 4), st);
+      launch_finalize<double>(clock(), part, nb, p.cfl, 0, 0, probe_args(), u(cur), nullptr, st);
+    }
   }
 
   void drop_graphs() {
@@ -366,7 +395,8 @@ int icr_create(const icr_grid* g, const icr_phys* p, void* ws, size_t ws_bytes, 
   s->gm = p->gravity ? kGM / (s->un.len * s->un.v * s->un.v) : 0.0;
   s->dph = 2.0 * kPi / g->n_phi;
   s->tile_r = 64;
-  s->variant = 1;
+  s->variant = 2;
+  s->planes = 8;
   s->use_graphs = 1;
   s->graphs_ok = false;
   hipError_t e = hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking);
@@ -785,20 +815,24 @@ int icr_profile_steps(icr_solver* s, int n, double* avg_ms) {
   }
   for (int q = 0; q < 5; ++q) (void)hipEventDestroy(ev[q]);
   for (int k = 0; k < 4; ++k) avg_ms[k] = acc[k] / n;
-  if (!s->logging()) avg_ms[3] = 0.0;
   return rc;
 }
 
-int icr_set_launch(icr_solver* s, int variant, int tile_r, int tile_t, int use_graphs) {
+int icr_set_launch(icr_solver* s, int variant, int tile_r, int planes, int use_graphs) {
   if (!s) return fail(ICR_ERR_ARG, "solver is NULL");
-  if (variant != 0 && variant != 1) return fail(ICR_ERR_ARG, "variant must be 0 or 1");
+  if (variant == 0) variant = 2;
+  if (variant != 1 && variant != 2) return fail(ICR_ERR_ARG, "variant must be 0, 1 or 2");
   if (tile_r == 0) tile_r = 64;
-  if (tile_t == 0) tile_t = 256 / tile_r;
-  if (!((tile_r == 64 && tile_t == 4) || (tile_r == 128 && tile_t == 2) ||
-        (tile_r == 256 && tile_t == 1)))
-    return fail(ICR_ERR_ARG, "tile (%d, %d) not one of (64,4), (128,2), (256,1)", tile_r, tile_t);
-  s->variant = variant ? variant : 1;
+  if (variant == 1 && tile_r != 64 && tile_r != 128 && tile_r != 256)
+    return fail(ICR_ERR_ARG, "variant 1 tile_r must be 64, 128 or 256 (got %d)", tile_r);
+  if (variant == 2 && tile_r != 32 && tile_r != 64)
+    return fail(ICR_ERR_ARG, "variant 2 tile_r must be 32 or 64 (got %d)", tile_r);
+  if (planes == 0) planes = 8;
+  if (planes < 1 || planes > s->g.n_phi)
+    return fail(ICR_ERR_ARG, "planes must be in [1, n_phi] (got %d)", planes);
+  s->variant = variant;
   s->tile_r = tile_r;
+  s->planes = planes;
   s->use_graphs = use_graphs ? 1 : 0;
   s->drop_graphs();
   return ICR_OK;

@@ -51,10 +51,47 @@ __device__ __forceinline__ R rmax(R a, R b) { return a > b ? a : b; }
 template <typename R>
 __device__ __forceinline__ R rmin(R a, R b) { return a < b ? a : b; }
 
+// Reciprocal and square root for the face-once kernel.  FP64: the hardware
+// estimate refined by Newton-Raphson (reciprocal, y <- y + y (1 - x y),
+// twice) or by Goldschmidt's coupled iteration for g ~ sqrt(x),
+// h ~ 1/(2 sqrt(x)) (twice, then one residual correction); both end within
+// about one ulp for normal positive x.  FP32: the single hardware op.
+__device__ __forceinline__ double rcp_fast(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  double e = __builtin_fma(-x, y, 1.0);
+  y = __builtin_fma(y, e, y);
+  e = __builtin_fma(-x, y, 1.0);
+  return __builtin_fma(y, e, y);
+}
+__device__ __forceinline__ float rcp_fast(float x) { return __builtin_amdgcn_rcpf(x); }
+
+__device__ __forceinline__ double sqrt_fast(double x) {  // x > 0
+  const double y = __builtin_amdgcn_rsq(x);
+  double g = x * y, h = 0.5 * y;
+  double r = __builtin_fma(-g, h, 0.5);
+  g = __builtin_fma(g, r, g);
+  h = __builtin_fma(h, r, h);
+  r = __builtin_fma(-g, h, 0.5);
+  g = __builtin_fma(g, r, g);
+  h = __builtin_fma(h, r, h);
+  const double d = __builtin_fma(-g, g, x);
+  return __builtin_fma(d, h, g);
+}
+__device__ __forceinline__ float sqrt_fast(float x) { return __builtin_amdgcn_sqrtf(x); }
+
+// Smallest positive argument passed to sqrt_fast for a square root that may
+// be exactly zero (keeps the estimate finite; far below any resolved value).
 template <typename R>
+__device__ __forceinline__ R sqrt_floor();
+template <>
+__device__ __forceinline__ double sqrt_floor<double>() { return 1e-280; }
+template <>
+__device__ __forceinline__ float sqrt_floor<float>() { return 1e-30f; }
+
+template <typename R, bool FAST = false>
 __device__ __forceinline__ void cons2prim(const R (&u)[NV], R (&w)[NV], R gm1) {
   const R rho = u[0];
-  const R ir = R(1) / rho;
+  const R ir = FAST ? rcp_fast(rho) : R(1) / rho;
   w[0] = rho;
   w[1] = u[1] * ir;
   w[2] = u[2] * ir;
@@ -84,14 +121,19 @@ __device__ __forceinline__ void prim2cons(const R (&w)[NV], R (&u)[NV], R igm1) 
 
 // Fast magnetosonic speed along local component N (1..3):
 // c_f^2 = [a^2 + b^2 + sqrt((a^2 + b^2)^2 - 4 a^2 B_n^2 / rho)] / 2.
-template <typename R, int N>
+template <typename R, int N, bool FAST = false>
 __device__ __forceinline__ R cfast(const R (&w)[NV], R gam) {
-  const R ir = R(1) / w[0];
+  const R ir = FAST ? rcp_fast(w[0]) : R(1) / w[0];
   const R a2 = gam * w[4] * ir;
   const R b2 = (w[5] * w[5] + w[6] * w[6] + w[7] * w[7]) * ir;
   const R bn = w[4 + N];
   const R s = a2 + b2;
   R disc = s * s - R(4) * a2 * bn * bn * ir;
+  if (FAST) {
+    // floors keep exact zeros (possible only for invalid states) at ~0
+    disc = rmax(disc, sqrt_floor<R>());
+    return sqrt_fast(rmax(R(0.5) * (s + sqrt_fast(disc)), sqrt_floor<R>()));
+  }
   disc = rmax(disc, R(0));
   return sqrt(R(0.5) * (s + sqrt(disc)));
 }
@@ -111,8 +153,18 @@ __device__ __forceinline__ void phys_flux(const R (&w)[NV], const R (&u)[NV], R 
   for (int d = 1; d <= 3; ++d) f[4 + d] = vn * w[4 + d] - bn * w[d];
 }
 
-template <typename R, int LIM>
+// minmod(a, b): 0 if a b <= 0, else the argument of smaller magnitude.
+// MC(a, b): 0 if a b <= 0, else sign(a) min(2|a|, 2|b|, |a + b|/2).
+// FAST form: the same functions as max(min(x...), min(max(x...), 0)) over the
+// candidate slopes (2a, 2b, (a+b)/2 for MC), which is branch-free.
+template <typename R, int LIM, bool FAST = false>
 __device__ __forceinline__ R limiter(R a, R b) {
+  if (FAST) {
+    if (LIM == LIM_MINMOD) return fmax(fmin(a, b), fmin(fmax(a, b), R(0)));
+    const R x = R(2) * a, y = R(2) * b, z = R(0.5) * (a + b);
+    const R lo = fmin(fmin(x, y), z), hi = fmax(fmax(x, y), z);
+    return fmax(lo, fmin(hi, R(0)));
+  }
   if (a * b <= R(0)) return R(0);
   if (LIM == LIM_MINMOD) return fabs(a) < fabs(b) ? a : b;
   R m = rmin(R(2) * fabs(a), R(2) * fabs(b));
@@ -123,22 +175,22 @@ __device__ __forceinline__ R limiter(R a, R b) {
 // Face states from four consecutive cells (m-2, m-1, m, m+1) around face
 // m-1/2: W_L = W_{m-1} + s_{m-1}/2, W_R = W_m - s_m/2, limited undivided
 // slopes on primitives.
-template <typename R, int LIM>
+template <typename R, int LIM, bool FAST = false>
 __device__ __forceinline__ void reconstruct(const R (&a)[NV], const R (&b)[NV],
                                             const R (&c)[NV], const R (&d)[NV],
                                             R (&wl)[NV], R (&wr)[NV]) {
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     const R db = b[v] - a[v], dc = c[v] - b[v], dd = d[v] - c[v];
-    wl[v] = b[v] + R(0.5) * limiter<R, LIM>(db, dc);
-    wr[v] = c[v] - R(0.5) * limiter<R, LIM>(dc, dd);
+    wl[v] = b[v] + R(0.5) * limiter<R, LIM, FAST>(db, dc);
+    wr[v] = c[v] - R(0.5) * limiter<R, LIM, FAST>(dc, dd);
   }
 }
 
 // Numerical flux from the two face states: TVDLF
 // F = (F_L + F_R)/2 - alpha (U_R - U_L)/2, alpha = max(|v_n| + c_f), or HLL
 // with S_L = min(v_nL - c_fL, v_nR - c_fR), S_R = max(v_nL + c_fL, ...).
-template <typename R, int N, int FLUX>
+template <typename R, int N, int FLUX, bool FAST = false>
 __device__ __forceinline__ void face_flux(const R (&wl)[NV], const R (&wr)[NV],
                                           R gam, R igm1, R (&fs)[NV]) {
   R ul[NV], ur[NV], fl[NV], fr[NV];
@@ -146,7 +198,7 @@ __device__ __forceinline__ void face_flux(const R (&wl)[NV], const R (&wr)[NV],
   prim2cons<R>(wr, ur, igm1);
   phys_flux<R, N>(wl, ul, fl);
   phys_flux<R, N>(wr, ur, fr);
-  const R cl = cfast<R, N>(wl, gam), cr = cfast<R, N>(wr, gam);
+  const R cl = cfast<R, N, FAST>(wl, gam), cr = cfast<R, N, FAST>(wr, gam);
   if (FLUX == FLUX_TVDLF) {
     const R alpha = rmax(fabs(wl[N]) + cl, fabs(wr[N]) + cr);
 #pragma unroll
@@ -162,7 +214,7 @@ __device__ __forceinline__ void face_flux(const R (&wl)[NV], const R (&wr)[NV],
 #pragma unroll
       for (int v = 0; v < NV; ++v) fs[v] = fr[v];
     } else {
-      const R id = R(1) / (sr - sl);
+      const R id = FAST ? rcp_fast(sr - sl) : R(1) / (sr - sl);
 #pragma unroll
       for (int v = 0; v < NV; ++v)
         fs[v] = (sr * fl[v] - sl * fr[v] + sl * sr * (ur[v] - ul[v])) * id;

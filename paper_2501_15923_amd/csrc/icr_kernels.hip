@@ -6,12 +6,13 @@
 //                   time interpolation between maps (Sect. 3) and the
 //                   cone-CME overwrite (Sect. 3.2); one value serves both
 //                   ghost layers (Sect. 2.1)
-//   k_stage         fused reconstruct + flux + divergence + sources + RK2
-//                   combine (Sect. 2 Eqs. 1-6); stage 2 also reduces the
-//                   next CFL dt, the relaxation residual and the validity
-//                   flag, finishing in its last block
-//   k_cfl           CFL dt of the current state (after init / set_state)
-//   k_probe_*       trajectory interpolation, frame change and trilinear
+//   k_stage_v1      fused reconstruct + flux + divergence + sources + RK2
+//                   combine (Sect. 2 Eqs. 1-6), one thread per cell, every
+//                   neighbour converted on the fly (reference variant; the
+//                   default face-once variant is in icr_stage_lds.hip);
+//                   stage 2 also writes per-block CFL / residual partials
+//   k_cfl           CFL partials of the current state (after init / set_state)
+//   k_probe_sample  trajectory interpolation, frame change and trilinear
 //                   sampling on the stretched grid (Sect. 2)
 //
 // Layouts: state [8][n_phi][n_theta][n_r] (r fastest), ghost primitives
@@ -172,109 +173,6 @@ void launch_boundary_at(const BndArgs& a, double t, double* out, const Scale& sc
   hipLaunchKernelGGL(k_boundary_at, dim3((plane + 255) / 256), dim3(256), 0, s, a, t, out, sc);
 }
 
-// ------------------------------------------------------- reductions ------
-// Block of 256 threads: max of lam, sums of s1/s0 (fixed tree), min of bad.
-__device__ __forceinline__ void block_reduce(double& lam, double& s1, double& s0, int& bad,
-                                             double (*sh)[4]) {
-  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
-  for (int off = 32; off > 0; off >>= 1) {
-    lam = fmax(lam, __shfl_xor(lam, off, 64));
-    s1 += __shfl_xor(s1, off, 64);
-    s0 += __shfl_xor(s0, off, 64);
-    const int ob = __shfl_xor(bad, off, 64);
-    bad = ob < bad ? ob : bad;
-  }
-  const int wv = tid >> 6, lane = tid & 63;
-  if (lane == 0) {
-    sh[wv][0] = lam;
-    sh[wv][1] = s1;
-    sh[wv][2] = s0;
-    sh[wv][3] = (double)bad;
-  }
-  __syncthreads();
-  if (tid == 0) {
-    const int nw = (blockDim.x * blockDim.y) >> 6;
-    for (int q = 1; q < nw; ++q) {
-      lam = fmax(lam, sh[q][0]);
-      s1 += sh[q][1];
-      s0 += sh[q][2];
-      const int b = (int)sh[q][3];
-      bad = b < bad ? b : bad;
-    }
-  }
-}
-
-__device__ void set_next_dt(DevClock* ck, double dtc) {
-  ck->dt_cfl = dtc;
-  if (ck->t_end > 0.0 && ck->t >= ck->t_end) {
-    ck->active = 0;
-    ck->dt = 0.0;
-    ck->clip = 0;
-    return;
-  }
-  if (ck->t_end > 0.0 && ck->t + dtc >= ck->t_end) {
-    ck->dt = ck->t_end - ck->t;
-    ck->clip = 1;
-  } else {
-    ck->dt = dtc;
-    ck->clip = 0;
-  }
-}
-
-// Publish the block partial; the last block to arrive reduces all partials
-// in a fixed order and updates the clock.  advance = 1 for the end of an
-// RK2 step, 0 for a plain CFL evaluation.
-__device__ void finish_reduction(DevClock* ck, double* partials, int nblocks, double cfl,
-                                 int advance, double lam, double s1, double s0, int bad) {
-  __shared__ double sh[4][4];
-  __shared__ int am_last;
-  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
-  const int bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
-  block_reduce(lam, s1, s0, bad, sh);
-  if (tid == 0) {
-    __hip_atomic_store(&partials[4 * bid + 0], lam, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&partials[4 * bid + 1], s1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&partials[4 * bid + 2], s0, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_store(&partials[4 * bid + 3], (double)bad, __ATOMIC_RELAXED,
-                       __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
-    const unsigned prev = atomicAdd(&ck->counter, 1u);
-    am_last = (prev == (unsigned)(nblocks - 1));
-  }
-  __syncthreads();
-  if (!am_last) return;
-  __threadfence();
-  double l = 0.0, a1 = 0.0, a0 = 0.0;
-  int b = BAD_NONE;
-  for (int q = tid; q < nblocks; q += blockDim.x * blockDim.y) {
-    l = fmax(l, __hip_atomic_load(&partials[4 * q + 0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
-    a1 += __hip_atomic_load(&partials[4 * q + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    a0 += __hip_atomic_load(&partials[4 * q + 2], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    const int qb = (int)__hip_atomic_load(&partials[4 * q + 3], __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT);
-    b = qb < b ? qb : b;
-  }
-  __syncthreads();
-  block_reduce(l, a1, a0, b, sh);
-  if (tid == 0) {
-    if (advance) {
-      ck->t = ck->clip ? ck->t_end : ck->t + ck->dt;
-      ck->step += 1;
-      ck->taken += 1;
-      ck->last_dt = ck->dt;
-      ck->resid = sqrt(a1) / sqrt(a0);
-      ck->advanced = 1;
-    }
-    if (b != BAD_NONE) {
-      if (ck->bad == BAD_NONE || b < ck->bad) ck->bad = b;
-      ck->active = 0;
-    }
-    set_next_dt(ck, cfl / l);
-    if (ck->bad != BAD_NONE) ck->active = 0;
-    ck->counter = 0;
-  }
-}
-
 __global__ void k_clock_begin(DevClock* ck, double t_end) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   ck->t_end = t_end;
@@ -305,24 +203,6 @@ __device__ __forceinline__ void load_prim(const StageArgs<R>& a, int i, int j, i
 #pragma unroll
   for (int v = 0; v < NV; ++v) u[v] = a.uin[v * a.ncell + c];
   cons2prim<R>(u, w, a.gm1);
-}
-
-// CFL rate of one cell from its primitives: sum_d (|v_d| + c_f,d) / dx_d.
-template <typename R>
-__device__ __forceinline__ double cell_rate(const R (&w)[NV], const Metric<R>& m, int i, int j,
-                                            R gam) {
-  const R lr = (fabs(w[1]) + cfast<R, 1>(w, gam)) * m.idr[i];
-  const R lt = (fabs(w[2]) + cfast<R, 2>(w, gam)) * m.irc[i] * m.ilth;
-  const R lp = (fabs(w[3]) + cfast<R, 3>(w, gam)) * m.irc[i] * m.ilph[j];
-  return (double)(lr + lt + lp);
-}
-
-template <typename R>
-__device__ __forceinline__ bool cell_valid(const R (&u)[NV], const R (&w)[NV]) {
-  bool ok = w[0] > R(0) && w[4] > R(0);
-#pragma unroll
-  for (int v = 0; v < NV; ++v) ok = ok && isfinite(u[v]);
-  return ok;
 }
 
 template <typename R, int FLUX, int LIM, int STAGE>
@@ -420,9 +300,7 @@ __global__ void __launch_bounds__(256) k_stage_v1(StageArgs<R> a) {
       }
     }
   }
-  if (STAGE == 2 && active)
-    finish_reduction(a.clock, a.partials, gridDim.x * gridDim.y * gridDim.z, a.cfl, 1, lam, s1,
-                     s0, bad);
+  if (STAGE == 2 && active) write_partials(a.partials, lam, s1, s0, bad);
 }
 
 // CFL dt of the current state; no time advance.
@@ -442,8 +320,7 @@ __global__ void __launch_bounds__(256) k_cfl(StageArgs<R> a) {
     lam = cell_rate<R>(w, a.m, i, j, a.gam);
   }
   // invalid cells are reported by the next step, not here
-  finish_reduction(a.clock, a.partials, gridDim.x * gridDim.y * gridDim.z, a.cfl, 0, lam, 0.0,
-                   0.0, bad);
+  write_partials(a.partials, lam, 0.0, 0.0, bad);
 }
 
 template <typename R, int FLUX, int LIM>
@@ -573,80 +450,6 @@ template void launch_export<float>(const void*, double*, long long, int, const S
                                    hipStream_t);
 
 // ---------------------------------------------------------------- probes --
-// Position from the trajectory table at time t (clamped), co-rotating
-// longitude phi - Omega t, trilinear interpolation of the primitives between
-// the 8 surrounding cell centres (linear in r on the stretched grid,
-// periodic in phi), v_phi returned in the inertial frame.
-template <typename R>
-__device__ void probe_eval(const ProbeArgs& a, const R* __restrict__ u, int q, double tcode,
-                           double* o) {
-  const double ts = tcode * a.sc.t;
-  const double* tb = a.traj + (long long)q * a.npts * 4;
-  double pos[4];
-  const int np = a.npts;
-  if (np == 1 || ts <= tb[0]) {
-    for (int e = 0; e < 4; ++e) pos[e] = tb[e];
-  } else if (ts >= tb[(np - 1) * 4]) {
-    for (int e = 0; e < 4; ++e) pos[e] = tb[(np - 1) * 4 + e];
-  } else {
-    int lo = 0, hi = np - 1;
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (tb[mid * 4] <= ts) lo = mid; else hi = mid;
-    }
-    const double al = (ts - tb[lo * 4]) / (tb[(lo + 1) * 4] - tb[lo * 4]);
-    pos[0] = ts;
-    for (int e = 1; e < 4; ++e) pos[e] = (1.0 - al) * tb[lo * 4 + e] + al * tb[(lo + 1) * 4 + e];
-  }
-  const double twopi = 6.283185307179586476925286766559;
-  const double r = pos[1] / a.sc.len, th = pos[2];
-  double ph = pos[3] - a.omega * tcode;
-  ph = ph - floor(ph / twopi) * twopi;
-  o[0] = ts;
-  o[1] = pos[1];
-  o[2] = th;
-  o[3] = ph;
-  const int nr = a.nr, nt = a.nt, nph = a.np;
-  const double* rc = a.rc;
-  const double* tc = a.tc;
-  if (!(r >= rc[0] && r <= rc[nr - 1] && th >= tc[0] && th <= tc[nt - 1])) {
-    for (int v = 0; v < NV; ++v) o[4 + v] = __builtin_nan("");
-    return;
-  }
-  int lo = 0, hi = nr - 1;  // rc[lo] <= r, lo <= nr-2
-  while (hi - lo > 1) {
-    const int mid = (lo + hi) >> 1;
-    if (rc[mid] <= r) lo = mid; else hi = mid;
-  }
-  const int i = lo;
-  int jl = 0, jh = nt - 1;
-  while (jh - jl > 1) {
-    const int mid = (jl + jh) >> 1;
-    if (tc[mid] <= th) jl = mid; else jh = mid;
-  }
-  const int j = jl;
-  const double fk = (ph - 0.5 * a.dph) / a.dph;
-  const int k0 = (int)floor(fk);
-  const double az = fk - k0;
-  const int ka = ((k0 % nph) + nph) % nph, kb = (ka + 1) % nph;
-  const double ax = (r - rc[i]) / (rc[i + 1] - rc[i]);
-  const double ay = (th - tc[j]) / (tc[j + 1] - tc[j]);
-  const long long n = (long long)nr * nt * nph;
-  double acc[NV] = {0, 0, 0, 0, 0, 0, 0, 0};
-  for (int cz = 0; cz < 2; ++cz)
-    for (int cy = 0; cy < 2; ++cy)
-      for (int cx = 0; cx < 2; ++cx) {
-        const double wt = (cx ? ax : 1.0 - ax) * (cy ? ay : 1.0 - ay) * (cz ? az : 1.0 - az);
-        const long long c = ((long long)(cz ? kb : ka) * nt + (j + cy)) * nr + (i + cx);
-        double uu[NV], w[NV];
-        for (int v = 0; v < NV; ++v) uu[v] = (double)u[v * n + c];
-        cons2prim<double>(uu, w, a.gam - 1.0);
-        for (int v = 0; v < NV; ++v) acc[v] += wt * w[v];
-      }
-  acc[3] += a.omega * r * sin(th);
-  for (int v = 0; v < NV; ++v) o[4 + v] = acc[v] * a.sc.s[v];
-}
-
 template <typename R>
 __global__ void k_probe_sample(ProbeArgs a, const DevClock* __restrict__ ck,
                                const R* __restrict__ u, double* __restrict__ out) {
@@ -654,50 +457,14 @@ __global__ void k_probe_sample(ProbeArgs a, const DevClock* __restrict__ ck,
   if (q < a.n) probe_eval<R>(a, u, q, ck->t, out + 12 * q);
 }
 
-// Append a record after a completed step when the cadence rule fires.
-template <typename R>
-__global__ void k_probe_log(ProbeArgs a, DevClock* ck, const R* __restrict__ u,
-                            double* __restrict__ log) {
-  const int q = threadIdx.x;
-  const int adv = ck->advanced;
-  const double t = ck->t;
-  long long idx = 0;
-  bool rec = adv != 0;
-  if (rec && a.cadence > 0.0) {
-    idx = (long long)floor(t * a.sc.t / a.cadence);
-    rec = idx > ck->last_sample;
-  }
-  const long long row = ck->n_log;
-  __syncthreads();
-  if (rec && row < a.log_rows && q < a.n)
-    probe_eval<R>(a, u, q, t, log + (row * a.max_probes + q) * 12);
-  __syncthreads();
-  if (q == 0) {
-    if (rec) {
-      ck->n_log = row + 1;
-      if (a.cadence > 0.0) ck->last_sample = idx;
-    }
-    ck->advanced = 0;
-  }
-}
-
 template <typename R>
 void launch_probe_sample(const ProbeArgs& a, const DevClock* ck, const void* u, double* out,
                          hipStream_t s) {
   hipLaunchKernelGGL(k_probe_sample<R>, dim3(1), dim3(64), 0, s, a, ck, (const R*)u, out);
 }
-template <typename R>
-void launch_probe_log(const ProbeArgs& a, DevClock* ck, const void* u, double* log,
-                      hipStream_t s) {
-  hipLaunchKernelGGL(k_probe_log<R>, dim3(1), dim3(64), 0, s, a, ck, (const R*)u, log);
-}
 template void launch_probe_sample<double>(const ProbeArgs&, const DevClock*, const void*, double*,
                                           hipStream_t);
 template void launch_probe_sample<float>(const ProbeArgs&, const DevClock*, const void*, double*,
                                          hipStream_t);
-template void launch_probe_log<double>(const ProbeArgs&, DevClock*, const void*, double*,
-                                       hipStream_t);
-template void launch_probe_log<float>(const ProbeArgs&, DevClock*, const void*, double*,
-                                      hipStream_t);
 
 }  // namespace icr

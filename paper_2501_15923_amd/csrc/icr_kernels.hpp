@@ -79,6 +79,163 @@ struct ProbeArgs {
   double dph;
 };
 
+
+// ------------------------------------------------------ shared helpers --
+// Block of 256 threads: max of lam, sums of s1/s0 (fixed tree), min of bad.
+__device__ __forceinline__ void block_reduce(double& lam, double& s1, double& s0, int& bad,
+                                             double (*sh)[4]) {
+  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+  for (int off = 32; off > 0; off >>= 1) {
+    lam = fmax(lam, __shfl_xor(lam, off, 64));
+    s1 += __shfl_xor(s1, off, 64);
+    s0 += __shfl_xor(s0, off, 64);
+    const int ob = __shfl_xor(bad, off, 64);
+    bad = ob < bad ? ob : bad;
+  }
+  const int wv = tid >> 6, lane = tid & 63;
+  if (lane == 0) {
+    sh[wv][0] = lam;
+    sh[wv][1] = s1;
+    sh[wv][2] = s0;
+    sh[wv][3] = (double)bad;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const int nw = (blockDim.x * blockDim.y) >> 6;
+    for (int q = 1; q < nw; ++q) {
+      lam = fmax(lam, sh[q][0]);
+      s1 += sh[q][1];
+      s0 += sh[q][2];
+      const int b = (int)sh[q][3];
+      bad = b < bad ? b : bad;
+    }
+  }
+}
+
+__device__ inline void set_next_dt(DevClock* ck, double dtc) {
+  ck->dt_cfl = dtc;
+  if (ck->t_end > 0.0 && ck->t >= ck->t_end) {
+    ck->active = 0;
+    ck->dt = 0.0;
+    ck->clip = 0;
+    return;
+  }
+  if (ck->t_end > 0.0 && ck->t + dtc >= ck->t_end) {
+    ck->dt = ck->t_end - ck->t;
+    ck->clip = 1;
+  } else {
+    ck->dt = dtc;
+    ck->clip = 0;
+  }
+}
+
+// Plain store of one block's partials; the finalize kernel reads them after
+// the kernel boundary.
+__device__ __forceinline__ void write_partials(double* partials, double lam, double s1, double s0,
+                                               int bad) {
+  __shared__ double sh[4][4];
+  block_reduce(lam, s1, s0, bad, sh);
+  if (threadIdx.x == 0 && threadIdx.y == 0) {
+    const int bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
+    partials[4 * bid + 0] = lam;
+    partials[4 * bid + 1] = s1;
+    partials[4 * bid + 2] = s0;
+    partials[4 * bid + 3] = (double)bad;
+  }
+}
+
+// CFL rate of one cell from its primitives: sum_d (|v_d| + c_f,d) / dx_d.
+template <typename R, bool FAST = false>
+__device__ __forceinline__ double cell_rate(const R (&w)[NV], const Metric<R>& m, int i, int j,
+                                            R gam) {
+  const R lr = (fabs(w[1]) + cfast<R, 1, FAST>(w, gam)) * m.idr[i];
+  const R lt = (fabs(w[2]) + cfast<R, 2, FAST>(w, gam)) * m.irc[i] * m.ilth;
+  const R lp = (fabs(w[3]) + cfast<R, 3, FAST>(w, gam)) * m.irc[i] * m.ilph[j];
+  return (double)(lr + lt + lp);
+}
+
+template <typename R>
+__device__ __forceinline__ bool cell_valid(const R (&u)[NV], const R (&w)[NV]) {
+  bool ok = w[0] > R(0) && w[4] > R(0);
+#pragma unroll
+  for (int v = 0; v < NV; ++v) ok = ok && isfinite(u[v]);
+  return ok;
+}
+
+// Position from the trajectory table at time t (clamped), co-rotating
+// longitude phi - Omega t, trilinear interpolation of the primitives between
+// the 8 surrounding cell centres (linear in r on the stretched grid,
+// periodic in phi), v_phi returned in the inertial frame.
+template <typename R>
+__device__ inline void probe_eval(const ProbeArgs& a, const R* __restrict__ u, int q, double tcode,
+                           double* o) {
+  const double ts = tcode * a.sc.t;
+  const double* tb = a.traj + (long long)q * a.npts * 4;
+  double pos[4];
+  const int np = a.npts;
+  if (np == 1 || ts <= tb[0]) {
+    for (int e = 0; e < 4; ++e) pos[e] = tb[e];
+  } else if (ts >= tb[(np - 1) * 4]) {
+    for (int e = 0; e < 4; ++e) pos[e] = tb[(np - 1) * 4 + e];
+  } else {
+    int lo = 0, hi = np - 1;
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (tb[mid * 4] <= ts) lo = mid; else hi = mid;
+    }
+    const double al = (ts - tb[lo * 4]) / (tb[(lo + 1) * 4] - tb[lo * 4]);
+    pos[0] = ts;
+    for (int e = 1; e < 4; ++e) pos[e] = (1.0 - al) * tb[lo * 4 + e] + al * tb[(lo + 1) * 4 + e];
+  }
+  const double twopi = 6.283185307179586476925286766559;
+  const double r = pos[1] / a.sc.len, th = pos[2];
+  double ph = pos[3] - a.omega * tcode;
+  ph = ph - floor(ph / twopi) * twopi;
+  o[0] = ts;
+  o[1] = pos[1];
+  o[2] = th;
+  o[3] = ph;
+  const int nr = a.nr, nt = a.nt, nph = a.np;
+  const double* rc = a.rc;
+  const double* tc = a.tc;
+  if (!(r >= rc[0] && r <= rc[nr - 1] && th >= tc[0] && th <= tc[nt - 1])) {
+    for (int v = 0; v < NV; ++v) o[4 + v] = __builtin_nan("");
+    return;
+  }
+  int lo = 0, hi = nr - 1;  // rc[lo] <= r, lo <= nr-2
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (rc[mid] <= r) lo = mid; else hi = mid;
+  }
+  const int i = lo;
+  int jl = 0, jh = nt - 1;
+  while (jh - jl > 1) {
+    const int mid = (jl + jh) >> 1;
+    if (tc[mid] <= th) jl = mid; else jh = mid;
+  }
+  const int j = jl;
+  const double fk = (ph - 0.5 * a.dph) / a.dph;
+  const int k0 = (int)floor(fk);
+  const double az = fk - k0;
+  const int ka = ((k0 % nph) + nph) % nph, kb = (ka + 1) % nph;
+  const double ax = (r - rc[i]) / (rc[i + 1] - rc[i]);
+  const double ay = (th - tc[j]) / (tc[j + 1] - tc[j]);
+  const long long n = (long long)nr * nt * nph;
+  double acc[NV] = {0, 0, 0, 0, 0, 0, 0, 0};
+  for (int cz = 0; cz < 2; ++cz)
+    for (int cy = 0; cy < 2; ++cy)
+      for (int cx = 0; cx < 2; ++cx) {
+        const double wt = (cx ? ax : 1.0 - ax) * (cy ? ay : 1.0 - ay) * (cz ? az : 1.0 - az);
+        const long long c = ((long long)(cz ? kb : ka) * nt + (j + cy)) * nr + (i + cx);
+        double uu[NV], w[NV];
+        for (int v = 0; v < NV; ++v) uu[v] = (double)u[v * n + c];
+        cons2prim<double>(uu, w, a.gam - 1.0);
+        for (int v = 0; v < NV; ++v) acc[v] += wt * w[v];
+      }
+  acc[3] += a.omega * r * sin(th);
+  for (int v = 0; v < NV; ++v) o[4 + v] = acc[v] * a.sc.s[v];
+}
+
 template <typename R>
 Metric<R> metric_view(const R* base, int nr, int nt, double dth);
 
@@ -105,7 +262,12 @@ template <typename R>
 void launch_probe_sample(const ProbeArgs& a, const DevClock* ck, const void* u, double* out,
                          hipStream_t s);
 template <typename R>
-void launch_probe_log(const ProbeArgs& a, DevClock* ck, const void* u, double* log,
-                      hipStream_t s);
+void launch_stage_lds(const StageArgs<R>& a, int stage, int flux, int lim, int tile_r,
+                      int kplanes, hipStream_t s);
+long long stage_lds_blocks(int nr, int nt, int np, int tile_r, int kplanes);
+template <typename R>
+void launch_finalize(DevClock* ck, const double* part, int nblocks, double cfl, int advance,
+                     int log_on, const ProbeArgs& pa, const void* u, double* log,
+                     hipStream_t s);
 
 }  // namespace icr

@@ -170,18 +170,25 @@ def test_zero_steps_and_t_end(mods):
 
 
 def test_tiling_graphs_and_determinism_bitwise(mods):
+    """Every tile / plane count / graph setting of a variant gives the same
+    bits (catches LDS halo races and chunk-boundary errors); the two
+    variants agree to rounding."""
     g = synth.Grid(150, 30, 20)
     times, maps = synth.dynamic_maps(g, 3, cadence=3600.0)
-    ref = None
-    for tile_r, graphs in ((64, 1), (128, 1), (256, 1), (64, 0), (64, 1)):
+    results = {}
+    for variant, tile_r, planes, graphs in (
+            (2, 64, 8, 1), (2, 32, 8, 1), (2, 64, 1, 1), (2, 64, 7, 1), (2, 32, 20, 1),
+            (2, 64, 8, 0), (2, 64, 8, 1),
+            (1, 64, 0, 1), (1, 128, 0, 1), (1, 256, 0, 1), (1, 64, 0, 0)):
         s, _ = pair(mods, g, times, maps)
-        s.set_launch(0, tile_r, 0, graphs)
+        s.set_launch(variant, tile_r, planes, graphs)
         s.step(23)
-        a = s.get_state(kind=1)
-        if ref is None:
-            ref = a
-        else:
-            assert np.array_equal(ref, a), (tile_r, graphs)
+        results.setdefault(variant, []).append(((tile_r, planes, graphs), s.get_state(kind=1)))
+    for variant, runs in results.items():
+        ref = runs[0][1]
+        for cfg, a in runs[1:]:
+            assert np.array_equal(ref, a), (variant, cfg)
+    assert parity.max_rel(results[1][0][1], results[2][0][1]) < 1e-12
 
 
 def test_restart_is_bitwise(mods):
