@@ -46,7 +46,81 @@ def parse():
                     help="HBM traffic per stage-2 launch measured with rocprofv3 counters")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device-to-device copy of known size (counter calibration)")
+    ap.add_argument("--workload", default="prod", choices=("prod", "ensemble"),
+                    help="prod: 600x60x120 dynamic run (the headline line); ensemble: 64 "
+                         "uneven runs in one persistent launch vs 64 sequential runs")
+    ap.add_argument("--runs", type=int, default=64)
     return ap.parse_args()
+
+
+def ensemble_bench(args):
+    """64 uneven runs (n_r 150-600, n_theta 30-60, n_phi 60-120, own map
+    sequences and cone CMEs) advanced K steps together, against the same 64
+    runs advanced one after the other with the single-run path."""
+    import torch
+
+    from paper_2501_15923_amd import autotune, synth
+    from paper_2501_15923_amd.ensemble import Ensemble
+    from paper_2501_15923_amd.solver import Solver
+
+    members = synth.ensemble_members(args.runs)
+    grids = [m["grid"] for m in members]
+    cells = sum(g.cells for g in grids)
+    log(f"bench: ensemble of {len(grids)} runs, {cells / 1e6:.1f} M cells, fp{args.precision}")
+    persistent, planes = autotune.tune_ensemble(grids, precision=args.precision)
+    log(f"bench: autotuner chose persistent={persistent}, planes {sorted(set(planes))}")
+    e = Ensemble(grids, precision=args.precision)
+    for m, run in zip(members, e.runs):
+        run.set_maps(m["times"], m["maps"])
+        run.set_cmes(m["cme"][None])
+        run.init_radial()
+    for r, p in enumerate(planes):
+        e.set_planes(r, p)
+    e.set_mode(persistent, 0, 1)
+    e.step(args.warmup)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    info = e.step(args.steps)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    assert all(i["steps"] == args.steps and i["status"] == 0 for i in info)
+    e.close()
+    del e
+    torch.cuda.empty_cache()
+    value = cells * args.steps / (ms * 1e-3)
+    log(f"bench: ensemble {args.steps} steps in {ms:.1f} ms")
+    seq_ms = 0.0
+    for m in members:
+        s = Solver(m["grid"], precision=args.precision)
+        s.set_maps(m["times"], m["maps"])
+        s.set_cmes(m["cme"][None])
+        s.init_radial()
+        s.set_launch(2, *autotune.tune_solver(m["grid"], precision=args.precision), 1)
+        s.step(args.warmup)
+        torch.cuda.synchronize()
+        ev0.record()
+        s.step(args.steps)
+        ev1.record()
+        torch.cuda.synchronize()
+        seq_ms += ev0.elapsed_time(ev1)
+        s.close()
+    seq = cells * args.steps / (seq_ms * 1e-3)
+    log(f"bench: sequential {args.steps} steps x {len(grids)} runs in {seq_ms:.1f} ms")
+    out = {
+        "metric": "ensemble aggregate MHD cell-updates/s", "value": value,
+        "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": f"f{args.precision}", "data": "synthetic",
+        "config": {"workload": f"ensemble_{len(grids)}_uneven_runs", "cells": cells,
+                   "persistent": int(persistent), "planes": sorted(set(planes))},
+        "sequential": {"value": seq, "unit": "cell-updates/s",
+                       "ms_per_step": seq_ms / args.steps},
+        "speedup_vs_sequential": value / seq,
+    }
+    print(json.dumps(out), flush=True)
 
 
 def copy_calibration():
@@ -92,6 +166,9 @@ def main():
               "sharding of this path is a design note, not a measured configuration.",
               file=sys.stderr)
         sys.exit(2)
+    if args.workload == "ensemble":
+        ensemble_bench(args)
+        return
     import numpy as np
     import torch
 

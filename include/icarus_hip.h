@@ -238,6 +238,52 @@ int icr_set_launch(icr_solver *s, int variant, int tile_r, int planes,
  * dt and probe record).  Same results as icr_step. */
 int icr_profile_steps(icr_solver *s, int n_steps, double *avg_ms);
 
+/* ------------------------------------------------------------------------
+ * Batched ensemble (not in the paper; many independent runs on one GPU).
+ * n_runs solvers with their own grids, boundary maps, cone CMEs, clocks and
+ * CFL dt, stepped together: each ensemble step walks all runs' boundary
+ * columns, stage-1 tiles, stage-2 tiles and per-run finalize.  In the
+ * persistent mode one kernel launch performs the steps with a device-wide
+ * barrier between those phases (its grid never exceeds the resident block
+ * capacity; a barrier that cannot complete turns into ICR_ERR_HIP instead of
+ * a hang); in the batched mode each phase is one launch.  Steps are replayed
+ * from captured HIP graphs.  Every run's state is bit-identical to stepping
+ * that run alone with icr_step.
+ * ------------------------------------------------------------------------ */
+typedef struct icr_ensemble icr_ensemble;
+
+/* Device bytes for n_runs grids (grids[n_runs]) sharing one icr_phys. */
+int icr_ens_workspace_bytes(int n_runs, const icr_grid *grids,
+                            const icr_phys *phys, size_t *bytes);
+
+/* Create the ensemble in caller-owned device memory (256-byte aligned). */
+int icr_ens_create(int n_runs, const icr_grid *grids, const icr_phys *phys,
+                   void *dev_workspace, size_t workspace_bytes,
+                   void *hip_stream, icr_ensemble **out);
+
+/* Release the ensemble and its run solvers (not the workspace). */
+void icr_ens_destroy(icr_ensemble *e);
+
+/* The solver of run r (owned by the ensemble): use it with
+ * icr_set_boundary_maps, icr_set_cmes, icr_init_radial, icr_set_state,
+ * icr_get_state and icr_get_clock.  Do not destroy it. */
+int icr_ens_run(icr_ensemble *e, int r, icr_solver **out);
+
+/* Phi planes per tile for run r (1..n_phi); the autotuner's knob.  The
+ * result does not depend on it. */
+int icr_ens_set_planes(icr_ensemble *e, int r, int planes);
+
+/* persistent: 1 (default) one launch for many steps, 0 one launch per phase;
+ * grid_blocks: 0 = all resident blocks, else a multiple of 8 not above that;
+ * use_graphs: 1 replays chunks of 8 steps from a captured HIP graph. */
+int icr_ens_set_mode(icr_ensemble *e, int persistent, int grid_blocks,
+                     int use_graphs);
+
+/* Advance every run n_steps RK2 steps (each with its own dt).  info: NULL or
+ * an array of n_runs results.  ICR_ERR_NONPHYSICAL if any run produced an
+ * invalid cell (that run stops advancing, the others continue). */
+int icr_ens_step(icr_ensemble *e, int n_steps, icr_step_info *info);
+
 #ifdef __cplusplus
 }
 #endif

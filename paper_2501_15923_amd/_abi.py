@@ -78,6 +78,15 @@ SIGNATURES = {
     "icr_boundary_at": (I, [P, ctypes.c_double, D]),
     "icr_set_launch": (I, [P, I, I, I, I]),
     "icr_profile_steps": (I, [P, I, D]),
+    "icr_ens_workspace_bytes": (I, [I, ctypes.POINTER(IcrGrid), ctypes.POINTER(IcrPhys),
+                                    ctypes.POINTER(ctypes.c_size_t)]),
+    "icr_ens_create": (I, [I, ctypes.POINTER(IcrGrid), ctypes.POINTER(IcrPhys), P,
+                           ctypes.c_size_t, P, ctypes.POINTER(P)]),
+    "icr_ens_destroy": (None, [P]),
+    "icr_ens_run": (I, [P, I, ctypes.POINTER(P)]),
+    "icr_ens_set_planes": (I, [P, I, I]),
+    "icr_ens_set_mode": (I, [P, I, I, I]),
+    "icr_ens_step": (I, [P, I, ctypes.POINTER(IcrStepInfo)]),
 }
 
 

@@ -13,6 +13,7 @@
 #include <vector>
 
 #include "icarus_hip.h"
+#include "icr_ensemble.hpp"
 #include "icr_kernels.hpp"
 
 using namespace icr;
@@ -835,6 +836,313 @@ int icr_set_launch(icr_solver* s, int variant, int tile_r, int planes, int use_g
   s->planes = planes;
   s->use_graphs = use_graphs ? 1 : 0;
   s->drop_graphs();
+  return ICR_OK;
+}
+
+}  // extern "C"
+
+// ======================================================================
+// Batched ensemble
+// ======================================================================
+struct icr_ensemble {
+  int n;
+  icr_phys p;
+  bool f32;
+  hipStream_t stream, cap_stream;
+  char* ws;
+  size_t table_bytes;
+  std::vector<icr_solver*> runs;
+  std::vector<int> planes;
+  // device tables
+  void* d_runs;
+  int* d_tile_off;
+  int* d_bnd_off;
+  GridBar* d_bar;
+  DevClock** d_clocks;
+  DevClock* d_gather;
+  int n_tiles, n_bitems;
+  int persistent, grid, use_graphs;
+  long long spin_limit;
+  hipGraphExec_t g_chunk;
+  bool graph_ok;
+  int graph_n;
+};
+
+namespace {
+
+size_t ens_table_bytes(int n) {
+  size_t b = 0;
+  b += align_up(sizeof(RunDesc<double>) * n);
+  b += 2 * align_up(sizeof(int) * (n + 1));
+  b += align_up(sizeof(GridBar));
+  b += align_up(sizeof(DevClock*) * n);
+  b += align_up(sizeof(DevClock) * n);
+  return b;
+}
+
+template <typename R>
+RunDesc<R> make_desc(icr_solver* s, int planes) {
+  RunDesc<R> d;
+  for (int p = 0; p < 2; ++p) {
+    d.s1[p] = s->stage_args<R>(p, p, 2, 0);
+    d.s2[p] = s->stage_args<R>(2, p, p ^ 1, 1);
+  }
+  d.bnd = s->bnd();
+  d.ghost0 = (R*)s->ghost(0);
+  d.ghost1 = (R*)s->ghost(1);
+  d.clock = s->clock();
+  d.partials = (double*)(s->ws + s->L.partials);
+  d.nbx = (s->g.n_r + 63) / 64;
+  d.nby = (s->g.n_theta + 3) / 4;
+  d.nbz = (s->g.n_phi + planes - 1) / planes;
+  d.planes = planes;
+  d.par = s->cur;
+  d.cfl = s->p.cfl;
+  return d;
+}
+
+int ens_upload(icr_ensemble* e) {
+  const int n = e->n;
+  std::vector<int> toff(n + 1, 0), boff(n + 1, 0);
+  std::vector<char> host(sizeof(RunDesc<double>) * n);
+  for (int r = 0; r < n; ++r) {
+    icr_solver* s = e->runs[r];
+    if (e->f32) {
+      RunDesc<float> d = make_desc<float>(s, e->planes[r]);
+      std::memcpy(host.data() + sizeof(RunDesc<float>) * r, &d, sizeof d);
+      toff[r + 1] = toff[r] + d.nbx * d.nby * d.nbz;
+    } else {
+      RunDesc<double> d = make_desc<double>(s, e->planes[r]);
+      std::memcpy(host.data() + sizeof(RunDesc<double>) * r, &d, sizeof d);
+      toff[r + 1] = toff[r] + d.nbx * d.nby * d.nbz;
+    }
+    boff[r + 1] = boff[r] + (s->g.n_theta * s->g.n_phi + 255) / 256;
+  }
+  e->n_tiles = toff[n];
+  e->n_bitems = boff[n];
+  const size_t rb = e->f32 ? sizeof(RunDesc<float>) * n : sizeof(RunDesc<double>) * n;
+  HIP_TRY(hipMemcpyAsync(e->d_runs, host.data(), rb, hipMemcpyHostToDevice, e->stream));
+  HIP_TRY(hipMemcpyAsync(e->d_tile_off, toff.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice,
+                         e->stream));
+  HIP_TRY(hipMemcpyAsync(e->d_bnd_off, boff.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice,
+                         e->stream));
+  HIP_TRY(hipStreamSynchronize(e->stream));
+  return ICR_OK;
+}
+
+EnsLaunch ens_launch_args(icr_ensemble* e, int nsteps) {
+  EnsLaunch L;
+  L.runs = e->d_runs;
+  L.e.n_runs = e->n;
+  L.e.n_tiles = e->n_tiles;
+  L.e.n_bitems = e->n_bitems;
+  L.e.tile_off = e->d_tile_off;
+  L.e.bnd_off = e->d_bnd_off;
+  L.e.bar = e->d_bar;
+  L.e.spin_limit = e->spin_limit;
+  L.persistent = e->persistent;
+  L.grid = e->grid;
+  L.nsteps = nsteps;
+  L.flux = e->p.flux;
+  L.lim = e->p.limiter;
+  return L;
+}
+
+void ens_drop_graph(icr_ensemble* e) {
+  if (e->graph_ok) (void)hipGraphExecDestroy(e->g_chunk);
+  e->graph_ok = false;
+}
+
+}  // namespace
+
+extern "C" {
+
+int icr_ens_workspace_bytes(int n, const icr_grid* grids, const icr_phys* phys, size_t* bytes) {
+  if (n < 1 || !grids || !bytes) return fail(ICR_ERR_ARG, "need n >= 1, grids and bytes");
+  size_t total = ens_table_bytes(n);
+  for (int r = 0; r < n; ++r) {
+    int rc = validate(&grids[r], phys);
+    if (rc) return rc;
+    total += align_up(make_layout(grids[r], *phys).total);
+  }
+  *bytes = total;
+  return ICR_OK;
+}
+
+int icr_ens_create(int n, const icr_grid* grids, const icr_phys* phys, void* ws, size_t bytes,
+                   void* stream, icr_ensemble** out) {
+  size_t need = 0;
+  int rc = icr_ens_workspace_bytes(n, grids, phys, &need);
+  if (rc) return rc;
+  if (!out) return fail(ICR_ERR_ARG, "out is NULL");
+  *out = nullptr;
+  if (!ws || bytes < need) return fail(ICR_ERR_ARG, "workspace too small: %zu < %zu", bytes, need);
+  if (((uintptr_t)ws & 255) != 0) return fail(ICR_ERR_ARG, "workspace must be 256-byte aligned");
+  icr_ensemble* e = new icr_ensemble();
+  e->n = n;
+  e->p = *phys;
+  e->f32 = phys->precision == ICR_PREC_F32;
+  e->stream = (hipStream_t)stream;
+  e->ws = (char*)ws;
+  e->table_bytes = ens_table_bytes(n);
+  char* t = e->ws;
+  e->d_runs = t;
+  t += align_up(sizeof(RunDesc<double>) * n);
+  e->d_tile_off = (int*)t;
+  t += align_up(sizeof(int) * (n + 1));
+  e->d_bnd_off = (int*)t;
+  t += align_up(sizeof(int) * (n + 1));
+  e->d_bar = (GridBar*)t;
+  t += align_up(sizeof(GridBar));
+  e->d_clocks = (DevClock**)t;
+  t += align_up(sizeof(DevClock*) * n);
+  e->d_gather = (DevClock*)t;
+  e->persistent = 1;
+  e->use_graphs = 1;
+  e->graph_ok = false;
+  e->graph_n = 0;
+  e->spin_limit = 1LL << 28;
+  e->planes.assign(n, 8);
+  if (hipStreamCreateWithFlags(&e->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    delete e;
+    return fail(ICR_ERR_HIP, "hipStreamCreate failed");
+  }
+  char* w = e->ws + e->table_bytes;
+  std::vector<DevClock*> clocks(n);
+  for (int r = 0; r < n; ++r) {
+    const size_t b = align_up(make_layout(grids[r], *phys).total);
+    icr_solver* s = nullptr;
+    rc = icr_create(&grids[r], phys, w, b, stream, &s);
+    if (rc) {
+      for (icr_solver* q : e->runs) icr_destroy(q);
+      (void)hipStreamDestroy(e->cap_stream);
+      delete e;
+      return rc;
+    }
+    e->runs.push_back(s);
+    clocks[r] = s->clock();
+    if (e->planes[r] > grids[r].n_phi) e->planes[r] = grids[r].n_phi;
+    w += b;
+  }
+  GridBar zero{};
+  HIP_TRY(hipMemcpyAsync(e->d_bar, &zero, sizeof zero, hipMemcpyHostToDevice, e->stream));
+  HIP_TRY(hipMemcpyAsync(e->d_clocks, clocks.data(), sizeof(DevClock*) * n,
+                         hipMemcpyHostToDevice, e->stream));
+  HIP_TRY(hipStreamSynchronize(e->stream));
+  int dev = 0, cus = 0;
+  HIP_TRY(hipGetDevice(&dev));
+  HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+  const int per_cu = ensemble_blocks_per_cu(e->f32, phys->flux, phys->limiter);
+  e->grid = (per_cu > 0 ? per_cu : 1) * cus;
+  e->grid -= e->grid % NXCD;
+  if (e->grid < NXCD) e->grid = NXCD;
+  *out = e;
+  return ICR_OK;
+}
+
+void icr_ens_destroy(icr_ensemble* e) {
+  if (!e) return;
+  (void)hipStreamSynchronize(e->stream);
+  ens_drop_graph(e);
+  for (icr_solver* s : e->runs) icr_destroy(s);
+  (void)hipStreamDestroy(e->cap_stream);
+  delete e;
+}
+
+int icr_ens_run(icr_ensemble* e, int r, icr_solver** out) {
+  if (!e || !out) return fail(ICR_ERR_ARG, "NULL argument");
+  if (r < 0 || r >= e->n) return fail(ICR_ERR_ARG, "run %d outside [0, %d)", r, e->n);
+  *out = e->runs[r];
+  return ICR_OK;
+}
+
+int icr_ens_set_planes(icr_ensemble* e, int r, int planes) {
+  if (!e) return fail(ICR_ERR_ARG, "ensemble is NULL");
+  if (r < 0 || r >= e->n) return fail(ICR_ERR_ARG, "run %d outside [0, %d)", r, e->n);
+  if (planes < 1 || planes > e->runs[r]->g.n_phi)
+    return fail(ICR_ERR_ARG, "planes must be in [1, n_phi]");
+  e->planes[r] = planes;
+  ens_drop_graph(e);
+  return ICR_OK;
+}
+
+int icr_ens_set_mode(icr_ensemble* e, int persistent, int grid_blocks, int use_graphs) {
+  if (!e) return fail(ICR_ERR_ARG, "ensemble is NULL");
+  if (grid_blocks < 0) return fail(ICR_ERR_ARG, "grid_blocks must be >= 0");
+  if (grid_blocks > 0) {
+    int dev = 0, cus = 0;
+    HIP_TRY(hipGetDevice(&dev));
+    HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    const int per_cu = ensemble_blocks_per_cu(e->f32, e->p.flux, e->p.limiter);
+    if (grid_blocks % NXCD != 0 || grid_blocks > per_cu * cus)
+      return fail(ICR_ERR_ARG, "grid_blocks must be a multiple of 8 and <= %d resident blocks",
+                  per_cu * cus);
+    e->grid = grid_blocks;
+  }
+  e->persistent = persistent ? 1 : 0;
+  e->use_graphs = use_graphs ? 1 : 0;
+  ens_drop_graph(e);
+  return ICR_OK;
+}
+
+int icr_ens_step(icr_ensemble* e, int n_steps, icr_step_info* info) {
+  if (!e) return fail(ICR_ERR_ARG, "ensemble is NULL");
+  if (n_steps < 0) return fail(ICR_ERR_ARG, "n_steps must be >= 0");
+  for (int r = 0; r < e->n; ++r) {
+    if (!e->runs[r]->have_maps || !e->runs[r]->have_state)
+      return fail(ICR_ERR_STATE, "run %d needs maps and a state", r);
+  }
+  int rc = ens_upload(e);
+  if (rc) return rc;
+  GridBar zero{};  // no ensemble kernel is in flight between calls
+  HIP_TRY(hipMemcpyAsync(e->d_bar, &zero, sizeof zero, hipMemcpyHostToDevice, e->stream));
+  launch_ens_clock_begin(e->d_clocks, e->n, e->stream);
+  // graphs replay an even chunk of steps; the parity in the tables is the
+  // parity at the start of each replay
+  constexpr int ECHUNK = 8;
+  int left = n_steps;
+  if (e->use_graphs && left >= ECHUNK) {
+    if (!e->graph_ok) {
+      hipGraph_t g;
+      HIP_TRY(hipStreamBeginCapture(e->cap_stream, hipStreamCaptureModeThreadLocal));
+      launch_ensemble(ens_launch_args(e, ECHUNK), e->f32, e->cap_stream);
+      HIP_TRY(hipStreamEndCapture(e->cap_stream, &g));
+      hipError_t ie = hipGraphInstantiate(&e->g_chunk, g, nullptr, nullptr, 0);
+      (void)hipGraphDestroy(g);
+      if (ie != hipSuccess) return fail(ICR_ERR_HIP, "hipGraphInstantiate failed");
+      e->graph_ok = true;
+    }
+    while (left >= ECHUNK) {
+      HIP_TRY(hipGraphLaunch(e->g_chunk, e->stream));
+      left -= ECHUNK;
+    }
+  }
+  if (left > 0)  // chunks keep the parity (ECHUNK is even): the tables still hold
+    launch_ensemble(ens_launch_args(e, left), e->f32, e->stream);
+  HIP_TRY(hipGetLastError());
+  for (icr_solver* s : e->runs) s->cur ^= (n_steps & 1);
+  launch_ens_gather(e->d_clocks, e->n, e->d_gather, e->stream);
+  std::vector<DevClock> c(e->n);
+  GridBar bar;
+  HIP_TRY(hipMemcpyAsync(c.data(), e->d_gather, sizeof(DevClock) * e->n, hipMemcpyDeviceToHost,
+                         e->stream));
+  HIP_TRY(hipMemcpyAsync(&bar, e->d_bar, sizeof bar, hipMemcpyDeviceToHost, e->stream));
+  HIP_TRY(hipStreamSynchronize(e->stream));
+  if (bar.error) return fail(ICR_ERR_HIP, "ensemble grid barrier timed out (blocks not resident)");
+  int status = ICR_OK;
+  for (int r = 0; r < e->n; ++r) {
+    const Units& u = e->runs[r]->un;
+    if (info) {
+      info[r].steps_taken = (int)c[r].taken;
+      info[r].status = c[r].bad == BAD_NONE ? ICR_OK : ICR_ERR_NONPHYSICAL;
+      info[r].bad_cell = c[r].bad == BAD_NONE ? -1 : c[r].bad;
+      info[r].t = c[r].t * u.t;
+      info[r].last_dt = c[r].last_dt * u.t;
+      info[r].residual = c[r].resid;
+    }
+    if (c[r].bad != BAD_NONE) status = ICR_ERR_NONPHYSICAL;
+  }
+  if (status) return fail(status, "a run produced a non-physical cell");
   return ICR_OK;
 }
 

@@ -1,0 +1,208 @@
+// icr_ensemble.hip -- batched ensemble of uneven runs on one GPU.
+//
+// Every run is a full solver (own grid, metric, maps, cone CMEs, clock and
+// CFL dt).  One step of the ensemble walks four work lists that span all
+// runs: boundary columns, stage-1 tiles, stage-2 tiles and one finalize per
+// run.  The persistent kernel executes n steps in a single launch with a
+// device-wide barrier between the lists; the batched mode launches one
+// kernel per list.  Both run the same tile code as the single-run kernels,
+// so each run's state is bit-identical to stepping it alone.
+#include "icr_ensemble.hpp"
+
+namespace icr {
+
+// Items [0, n) split into 8 contiguous XCD slices; block b serves slice
+// b % 8 with stride (blocks per XCD).
+template <typename F>
+__device__ __forceinline__ void for_items(int n, F&& f) {
+  const int G = gridDim.x, b = blockIdx.x;
+  const int xcd = b % NXCD, lb = b / NXCD, bpx = G / NXCD;
+  const int lo = (int)((long long)xcd * n / NXCD), hi = (int)((long long)(xcd + 1) * n / NXCD);
+  for (int it = lo + lb; it < hi; it += bpx) f(it);
+}
+
+__device__ __forceinline__ int find_run(const int* __restrict__ off, int n_runs, int item) {
+  int lo = 0, hi = n_runs;  // off[lo] <= item < off[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (off[mid] <= item) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+// Device-wide barrier (sense by generation count).  All blocks of the grid
+// must be resident; a bounded spin turns a missing block into an error flag
+// instead of a hang, and every block then leaves the kernel.
+__device__ bool grid_sync(GridBar* gb, unsigned nblocks, long long spin_limit) {
+  __shared__ int ok;
+  __syncthreads();
+  if (threadIdx.x == 0 && threadIdx.y == 0) {
+    ok = 1;
+    const unsigned g = __hip_atomic_load(&gb->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __threadfence();
+    const unsigned arrived = atomicAdd(&gb->count, 1u);
+    if (arrived == nblocks - 1) {
+      __hip_atomic_store(&gb->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      __threadfence();
+      atomicAdd(&gb->gen, 1u);
+    } else {
+      long long n = 0;
+      while (__hip_atomic_load(&gb->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        __builtin_amdgcn_s_sleep(2);
+        if (++n > spin_limit) {
+          atomicExch(&gb->error, 1);
+          ok = 0;
+          break;
+        }
+      }
+    }
+    if (__hip_atomic_load(&gb->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
+    __threadfence();
+  }
+  __syncthreads();
+  return ok != 0;
+}
+
+template <typename R>
+__device__ __forceinline__ void bnd_item(const RunDesc<R>* runs, const EnsTables& e, int item) {
+  const int r = find_run(e.bnd_off, e.n_runs, item);
+  const RunDesc<R>& rd = runs[r];
+  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+  const int q = (item - e.bnd_off[r]) * 256 + tid;
+  const int plane = rd.bnd.nt * rd.bnd.np;
+  if (q >= plane || !rd.clock->active) return;
+  const int j = q % rd.bnd.nt, k = q / rd.bnd.nt;
+  double w[NV];
+  boundary_prim(rd.bnd, rd.clock->t, j, k, w);
+  for (int v = 0; v < NV; ++v) rd.ghost0[(long long)v * plane + q] = (R)w[v];
+  boundary_prim(rd.bnd, rd.clock->t + rd.clock->dt, j, k, w);
+  for (int v = 0; v < NV; ++v) rd.ghost1[(long long)v * plane + q] = (R)w[v];
+}
+
+template <typename R, int FLUX, int LIM, int STAGE>
+__device__ __forceinline__ void stage_item(const RunDesc<R>* runs, const EnsTables& e, int item,
+                                           int step, StageSmem<R, 64, 4>& sm) {
+  const int r = find_run(e.tile_off, e.n_runs, item);
+  const RunDesc<R>& rd = runs[r];
+  const int local = item - e.tile_off[r];
+  const int par = (rd.par + step) & 1;
+  const int bx = local % rd.nbx, by = (local / rd.nbx) % rd.nby, bz = local / (rd.nbx * rd.nby);
+  stage_tile<R, 64, 4, FLUX, LIM, STAGE>(STAGE == 1 ? rd.s1[par] : rd.s2[par], rd.planes, bx, by,
+                                         bz, local, sm);
+}
+
+template <typename R>
+__device__ __forceinline__ void fin_item(const RunDesc<R>* runs, int r) {
+  const RunDesc<R>& rd = runs[r];
+  ProbeArgs none{};
+  finalize_run<R>(rd.clock, rd.partials, rd.nbx * rd.nby * rd.nbz, rd.cfl, 1, 0, none,
+                  (const R*)nullptr, nullptr);
+}
+
+template <typename R, int FLUX, int LIM>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_ensemble(const RunDesc<R>* __restrict__ runs, EnsTables e, int nsteps) {
+  const unsigned G = gridDim.x;
+  __shared__ StageSmem<R, 64, 4> sm;
+  for (int s = 0; s < nsteps; ++s) {
+    for_items(e.n_bitems, [&](int it) { bnd_item<R>(runs, e, it); });
+    if (!grid_sync(e.bar, G, e.spin_limit)) return;
+    for_items(e.n_tiles, [&](int it) { stage_item<R, FLUX, LIM, 1>(runs, e, it, s, sm); });
+    if (!grid_sync(e.bar, G, e.spin_limit)) return;
+    for_items(e.n_tiles, [&](int it) { stage_item<R, FLUX, LIM, 2>(runs, e, it, s, sm); });
+    if (!grid_sync(e.bar, G, e.spin_limit)) return;
+    for_items(e.n_runs, [&](int r) { fin_item<R>(runs, r); });
+    if (!grid_sync(e.bar, G, e.spin_limit)) return;
+  }
+}
+
+// ---- batched mode: one launch per work list (grid = items) ---------------
+template <typename R>
+__global__ void __launch_bounds__(256) k_ens_bnd(const RunDesc<R>* __restrict__ runs, EnsTables e) {
+  for_items(e.n_bitems, [&](int it) { bnd_item<R>(runs, e, it); });
+}
+template <typename R, int FLUX, int LIM, int STAGE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_ens_stage(const RunDesc<R>* __restrict__ runs, EnsTables e, int step) {
+  __shared__ StageSmem<R, 64, 4> sm;
+  for_items(e.n_tiles, [&](int it) { stage_item<R, FLUX, LIM, STAGE>(runs, e, it, step, sm); });
+}
+template <typename R>
+__global__ void __launch_bounds__(256) k_ens_fin(const RunDesc<R>* __restrict__ runs, EnsTables e) {
+  for_items(e.n_runs, [&](int r) { fin_item<R>(runs, r); });
+}
+
+__global__ void k_ens_clock_begin(DevClock* const* __restrict__ clocks, int n) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r >= n) return;
+  DevClock* ck = clocks[r];
+  ck->t_end = -1.0;
+  ck->taken = 0;
+  ck->active = ck->bad == BAD_NONE ? 1 : 0;
+  set_next_dt(ck, ck->dt_cfl);
+  if (ck->bad != BAD_NONE) ck->active = 0;
+}
+
+__global__ void k_ens_gather(DevClock* const* __restrict__ clocks, int n, DevClock* out) {
+  const int r = blockIdx.x * blockDim.x + threadIdx.x;
+  if (r < n) out[r] = *clocks[r];
+}
+
+template <typename R, int FLUX, int LIM>
+static void ens_launch(const EnsLaunch& L, hipStream_t s) {
+  const RunDesc<R>* runs = (const RunDesc<R>*)L.runs;
+  const dim3 blk(64, 4);
+  if (L.persistent) {
+    hipLaunchKernelGGL((k_ensemble<R, FLUX, LIM>), dim3(L.grid), blk, 0, s, runs, L.e, L.nsteps);
+    return;
+  }
+  auto items = [](int n) { return dim3((unsigned)((n + NXCD - 1) / NXCD * NXCD)); };
+  for (int q = 0; q < L.nsteps; ++q) {
+    hipLaunchKernelGGL(k_ens_bnd<R>, items(L.e.n_bitems), blk, 0, s, runs, L.e);
+    hipLaunchKernelGGL((k_ens_stage<R, FLUX, LIM, 1>), items(L.e.n_tiles), blk, 0, s, runs, L.e, q);
+    hipLaunchKernelGGL((k_ens_stage<R, FLUX, LIM, 2>), items(L.e.n_tiles), blk, 0, s, runs, L.e, q);
+    hipLaunchKernelGGL(k_ens_fin<R>, items(L.e.n_runs), blk, 0, s, runs, L.e);
+  }
+}
+
+template <typename R>
+static void ens_dispatch(const EnsLaunch& L, hipStream_t s) {
+  if (L.flux == FLUX_TVDLF) {
+    if (L.lim == LIM_MINMOD) ens_launch<R, FLUX_TVDLF, LIM_MINMOD>(L, s);
+    else ens_launch<R, FLUX_TVDLF, LIM_MC>(L, s);
+  } else {
+    if (L.lim == LIM_MINMOD) ens_launch<R, FLUX_HLL, LIM_MINMOD>(L, s);
+    else ens_launch<R, FLUX_HLL, LIM_MC>(L, s);
+  }
+}
+
+void launch_ensemble(const EnsLaunch& L, bool f32, hipStream_t s) {
+  if (f32) ens_dispatch<float>(L, s);
+  else ens_dispatch<double>(L, s);
+}
+
+void launch_ens_clock_begin(DevClock* const* clocks, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_ens_clock_begin, dim3((n + 63) / 64), dim3(64), 0, s, clocks, n);
+}
+
+void launch_ens_gather(DevClock* const* clocks, int n, DevClock* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_ens_gather, dim3((n + 63) / 64), dim3(64), 0, s, clocks, n, out);
+}
+
+int ensemble_blocks_per_cu(bool f32, int flux, int lim) {
+  int nb = 0;
+  const void* fn = nullptr;
+#define ICR_ENS_FN(R, F, L) reinterpret_cast<const void*>(&k_ensemble<R, F, L>)
+  if (f32)
+    fn = flux == FLUX_TVDLF ? (lim == LIM_MINMOD ? ICR_ENS_FN(float, 0, 0) : ICR_ENS_FN(float, 0, 1))
+                            : (lim == LIM_MINMOD ? ICR_ENS_FN(float, 1, 0) : ICR_ENS_FN(float, 1, 1));
+  else
+    fn = flux == FLUX_TVDLF
+             ? (lim == LIM_MINMOD ? ICR_ENS_FN(double, 0, 0) : ICR_ENS_FN(double, 0, 1))
+             : (lim == LIM_MINMOD ? ICR_ENS_FN(double, 1, 0) : ICR_ENS_FN(double, 1, 1));
+#undef ICR_ENS_FN
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 256, 0) != hipSuccess) return 0;
+  return nb;
+}
+
+}  // namespace icr

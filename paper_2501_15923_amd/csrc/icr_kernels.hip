@@ -92,47 +92,6 @@ void launch_metric(const MetricArgs& a, void* mr, bool f32, hipStream_t s) {
 }
 
 // ------------------------------------------------------------- boundary --
-// Primitive at the inner shell for column (j, k) at code time t.
-__device__ void boundary_prim(const BndArgs& a, double t, int j, int k, double (&w)[NV]) {
-  const long long plane = (long long)a.nt * a.np;
-  const long long q = (long long)j * a.np + k;
-  const int n = a.n_maps;
-  if (n == 1 || t <= a.tau[0]) {
-    for (int v = 0; v < NV; ++v) w[v] = a.maps[v * plane + q];
-  } else if (t >= a.tau[n - 1]) {
-    for (int v = 0; v < NV; ++v) w[v] = a.maps[((long long)(n - 1) * NV + v) * plane + q];
-  } else {
-    int lo = 0, hi = n - 1;  // tau[lo] <= t < tau[hi]
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (a.tau[mid] <= t) lo = mid; else hi = mid;
-    }
-    const double wgt = (t - a.tau[lo]) / (a.tau[lo + 1] - a.tau[lo]);
-    for (int v = 0; v < NV; ++v) {
-      const double x0 = a.maps[((long long)lo * NV + v) * plane + q];
-      const double x1 = a.maps[((long long)(lo + 1) * NV + v) * plane + q];
-      w[v] = (1.0 - wgt) * x0 + wgt * x1;
-    }
-  }
-  if (a.n_cme > 0) {
-    const double th = a.tc[j];
-    const double ph = (k + 0.5) * a.dph;
-    const double sth = sin(th), cth = cos(th);
-    for (int c = 0; c < a.n_cme; ++c) {
-      const double* m = a.cme + 8 * c;  // t0, dur, colat, lon, cos(hw), v, rho, p
-      if (!(t >= m[0] && t < m[0] + m[1])) continue;
-      const double cosd = cth * cos(m[2]) + sth * sin(m[2]) * cos(ph - m[3]);
-      if (cosd >= m[4]) {
-        w[0] = m[6];
-        w[1] = m[5];
-        w[2] = 0.0;
-        w[3] = -a.omega * a.r_in * sth;
-        w[4] = m[7];
-      }
-    }
-  }
-}
-
 template <typename R>
 __global__ void k_boundary(BndArgs a, const DevClock* __restrict__ ck, R* __restrict__ g1,
                            R* __restrict__ g2) {
@@ -300,7 +259,9 @@ __global__ void __launch_bounds__(256) k_stage_v1(StageArgs<R> a) {
       }
     }
   }
-  if (STAGE == 2 && active) write_partials(a.partials, lam, s1, s0, bad);
+  if (STAGE == 2 && active)
+    write_partials(a.partials, (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x,
+                   lam, s1, s0, bad);
 }
 
 // CFL dt of the current state; no time advance.
@@ -320,7 +281,8 @@ __global__ void __launch_bounds__(256) k_cfl(StageArgs<R> a) {
     lam = cell_rate<R>(w, a.m, i, j, a.gam);
   }
   // invalid cells are reported by the next step, not here
-  write_partials(a.partials, lam, 0.0, 0.0, bad);
+  write_partials(a.partials, (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x,
+                 lam, 0.0, 0.0, bad);
 }
 
 template <typename R, int FLUX, int LIM>

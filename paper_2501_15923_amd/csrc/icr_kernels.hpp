@@ -131,12 +131,11 @@ __device__ inline void set_next_dt(DevClock* ck, double dtc) {
 
 // Plain store of one block's partials; the finalize kernel reads them after
 // the kernel boundary.
-__device__ __forceinline__ void write_partials(double* partials, double lam, double s1, double s0,
-                                               int bad) {
+__device__ __forceinline__ void write_partials(double* partials, int bid, double lam, double s1,
+                                               double s0, int bad) {
   __shared__ double sh[4][4];
   block_reduce(lam, s1, s0, bad, sh);
   if (threadIdx.x == 0 && threadIdx.y == 0) {
-    const int bid = (blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x;
     partials[4 * bid + 0] = lam;
     partials[4 * bid + 1] = s1;
     partials[4 * bid + 2] = s0;
@@ -234,6 +233,47 @@ __device__ inline void probe_eval(const ProbeArgs& a, const R* __restrict__ u, i
       }
   acc[3] += a.omega * r * sin(th);
   for (int v = 0; v < NV; ++v) o[4 + v] = acc[v] * a.sc.s[v];
+}
+
+// Primitive at the inner shell for column (j, k) at code time t.
+__device__ inline void boundary_prim(const BndArgs& a, double t, int j, int k, double (&w)[NV]) {
+  const long long plane = (long long)a.nt * a.np;
+  const long long q = (long long)j * a.np + k;
+  const int n = a.n_maps;
+  if (n == 1 || t <= a.tau[0]) {
+    for (int v = 0; v < NV; ++v) w[v] = a.maps[v * plane + q];
+  } else if (t >= a.tau[n - 1]) {
+    for (int v = 0; v < NV; ++v) w[v] = a.maps[((long long)(n - 1) * NV + v) * plane + q];
+  } else {
+    int lo = 0, hi = n - 1;  // tau[lo] <= t < tau[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (a.tau[mid] <= t) lo = mid; else hi = mid;
+    }
+    const double wgt = (t - a.tau[lo]) / (a.tau[lo + 1] - a.tau[lo]);
+    for (int v = 0; v < NV; ++v) {
+      const double x0 = a.maps[((long long)lo * NV + v) * plane + q];
+      const double x1 = a.maps[((long long)(lo + 1) * NV + v) * plane + q];
+      w[v] = (1.0 - wgt) * x0 + wgt * x1;
+    }
+  }
+  if (a.n_cme > 0) {
+    const double th = a.tc[j];
+    const double ph = (k + 0.5) * a.dph;
+    const double sth = sin(th), cth = cos(th);
+    for (int c = 0; c < a.n_cme; ++c) {
+      const double* m = a.cme + 8 * c;  // t0, dur, colat, lon, cos(hw), v, rho, p
+      if (!(t >= m[0] && t < m[0] + m[1])) continue;
+      const double cosd = cth * cos(m[2]) + sth * sin(m[2]) * cos(ph - m[3]);
+      if (cosd >= m[4]) {
+        w[0] = m[6];
+        w[1] = m[5];
+        w[2] = 0.0;
+        w[3] = -a.omega * a.r_in * sth;
+        w[4] = m[7];
+      }
+    }
+  }
 }
 
 template <typename R>

@@ -1,228 +1,31 @@
-// icr_stage_lds.hip -- face-once fused stage kernel (default variant).
-//
-// One RK2 stage of the finite-volume update (Sect. 2 Eqs. 1-6) with every
-// face flux computed exactly once:
-//   - a block owns a TR x TT tile of (r, theta) columns and marches along
-//     phi over a chunk of planes;
-//   - per plane the primitives of the tile plus a two-cell halo in r and
-//     theta sit in LDS; r- and theta-face fluxes go to LDS and are shared by
-//     the two cells of each face;
-//   - the phi direction is carried in registers: each thread keeps the
-//     primitives of planes k-1 .. k+2 of its own column and the flux of
-//     face k-1/2 from the previous plane.
-// Lanes run along r, so global loads and stores are coalesced (state layout
-// [8][n_phi][n_theta][n_r]).  Stage 2 also forms the per-block partials of
-// the next CFL dt, of the relaxation residual and of the validity flag; a
-// one-block finalize kernel reduces them in a fixed order.
-#include "icr_kernels.hpp"
+// icr_stage_lds.hip -- single-run launches of the face-once stage kernel
+// and the finalize kernel (device code in icr_stage_lds.hpp).
+#include "icr_stage_lds.hpp"
 
 namespace icr {
-
-template <typename R, bool FAST>
-__device__ __forceinline__ void load_cons_prim(const StageArgs<R>& a, long long c, R (&w)[NV]) {
-  R u[NV];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) u[v] = a.uin[v * a.ncell + c];
-  cons2prim<R, FAST>(u, w, a.gm1);
-}
-
-__device__ __forceinline__ int wrap_phi(int k, int np) { return ((k % np) + np) % np; }
-
-constexpr int NXCD = 8;  // accelerator complex dies of MI355X
-
-// Face states of face m-1/2 from four LDS values per variable (p0..p3 =
-// cells m-2 .. m+1), then the numerical flux.
-template <typename R, int N, int FLUX, int LIM>
-__device__ __forceinline__ void lds_face(const R* base, int stride, R gam, R igm1, R (&f)[NV],
-                                         int vstride) {
-  R wl[NV], wr[NV];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    const R* q = base + v * vstride;
-    const R p0 = q[0], p1 = q[stride], p2 = q[2 * stride], p3 = q[3 * stride];
-    wl[v] = p1 + R(0.5) * limiter<R, LIM, true>(p1 - p0, p2 - p1);
-    wr[v] = p2 - R(0.5) * limiter<R, LIM, true>(p2 - p1, p3 - p2);
-  }
-  face_flux<R, N, FLUX, true>(wl, wr, gam, igm1, f);
-}
 
 #ifndef ICR_LDS_WAVES
 #define ICR_LDS_WAVES 2
 #endif
 
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2): XCD x gets a contiguous range of tiles (r fastest, then theta, then
+// phi) so that tiles sharing halos run on the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  const int xcd = b % NXCD, per = nb / NXCD, rem = nb % NXCD;
+  return xcd * per + (xcd < rem ? xcd : rem) + b / NXCD;
+}
+
 template <typename R, int TR, int TT, int FLUX, int LIM, int STAGE>
 __global__ void __launch_bounds__(TR* TT) __attribute__((amdgpu_waves_per_eu(ICR_LDS_WAVES)))
 k_stage_lds(StageArgs<R> a, int kplanes) {
-  constexpr int NT = TR * TT;
-  constexpr int WR = TR + 4, WT = TT + 4;
-  __shared__ R sW[NV][WT][WR];
-  __shared__ R sFr[NV][TT][TR + 1];
-  __shared__ R sFt[NV][TT + 1][TR];
-
-  const int ti = threadIdx.x, tj = threadIdx.y, tid = tj * TR + ti;
-  // Workgroups are dispatched round-robin over the 8 XCDs (each with its own
-  // L2): give XCD x a contiguous range of tiles (r fastest, then theta, then
-  // phi) so that tiles sharing halos run on the same L2.
   const int nbx = gridDim.x, nby = gridDim.y;
   const int nb = nbx * nby * gridDim.z;
   const int b = (blockIdx.z * nby + blockIdx.y) * nbx + blockIdx.x;
-  const int xcd = b % NXCD, per = nb / NXCD, rem = nb % NXCD;
-  const int tile = xcd * per + (xcd < rem ? xcd : rem) + b / NXCD;
-  const int bx = tile % nbx, by = (tile / nbx) % nby, bz = tile / (nbx * nby);
-  const int i0 = bx * TR, j0 = by * TT, k0 = bz * kplanes;
-  const int nr = a.nr, nt = a.nt, np = a.np;
-  const int kend = k0 + kplanes < np ? k0 + kplanes : np;
-  const int i = i0 + ti, j = j0 + tj;
-  const bool valid = i < nr && j < nt;
-  const int ic = i < nr ? i : nr - 1, jc = j < nt ? j : nt - 1;
-  const int active = a.clock->active;
-  const long long colbase = (long long)jc * nr + ic;  // + k * nt * nr
-  const long long plane_cells = (long long)nt * nr;
-
-  if (!active) {
-    if (STAGE == 2 && valid)
-      for (int k = k0; k < kend; ++k) {
-        const long long c = (long long)k * plane_cells + colbase;
-#pragma unroll
-        for (int v = 0; v < NV; ++v) a.uout[v * a.ncell + c] = a.un[v * a.ncell + c];
-      }
-    return;
-  }
-
-  // phi ring of the own column: at the top of iteration k, wa = W(k-1),
-  // wb = W(k), wc = W(k+1) and fcar = flux of face k-1/2.  Iteration k0-1
-  // only forms fcar, through the same code as every later phi face.
-  R wa[NV], wb[NV], wc[NV], fcar[NV];
-  load_cons_prim<R, true>(a, (long long)wrap_phi(k0 - 2, np) * plane_cells + colbase, wa);
-  load_cons_prim<R, true>(a, (long long)wrap_phi(k0 - 1, np) * plane_cells + colbase, wb);
-  load_cons_prim<R, true>(a, (long long)wrap_phi(k0, np) * plane_cells + colbase, wc);
-#pragma unroll
-  for (int v = 0; v < NV; ++v) fcar[v] = R(0);
-
-  double lam = 0.0, s1 = 0.0, s0 = 0.0;
-  int bad = BAD_NONE;
-  const long long gplane = (long long)nt * np;
-
-  for (int k = k0 - 1; k < kend; ++k) {
-    const bool body = k >= k0;  // uniform over the block
-    const long long kbase = (long long)k * plane_cells;
-    if (body) {
-      __syncthreads();  // the previous plane's LDS reads are complete
-#pragma unroll
-      for (int v = 0; v < NV; ++v) sW[v][tj + 2][ti + 2] = wb[v];
-      for (int h = tid; h < 4 * TR + 4 * TT; h += NT) {
-        int ii, jj;
-        if (h < 4 * TR) {
-          const int row = h / TR;
-          ii = h - row * TR;
-          jj = row < 2 ? row - 2 : TT + row - 2;
-        } else {
-          const int q = h - 4 * TR, s = q / TT;
-          jj = q - s * TT;
-          ii = s < 2 ? s - 2 : TR + s - 2;
-        }
-        int gi = i0 + ii, gj = j0 + jj;
-        gj = gj < 0 ? 0 : (gj >= nt ? nt - 1 : gj);
-        R w[NV];
-        if (gi < 0) {
-          const long long g = (long long)k * nt + gj;
-#pragma unroll
-          for (int v = 0; v < NV; ++v) w[v] = a.ghost[v * gplane + g];
-        } else {
-          gi = gi >= nr ? nr - 1 : gi;
-          load_cons_prim<R, true>(a, kbase + (long long)gj * nr + gi, w);
-        }
-#pragma unroll
-        for (int v = 0; v < NV; ++v) sW[v][jj + 2][ii + 2] = w[v];
-      }
-      __syncthreads();
-      // r face i-1/2 and theta face j-1/2 of each cell, plus the tile's
-      // last r face of every row and last theta face of every column
-      constexpr int VS = WT * WR;
-      {
-        R f[NV];
-        lds_face<R, 1, FLUX, LIM>(&sW[0][tj + 2][ti], 1, a.gam, a.igm1, f, VS);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) sFr[v][tj][ti] = f[v];
-      }
-      {
-        R f[NV];
-        lds_face<R, 2, FLUX, LIM>(&sW[0][tj][ti + 2], WR, a.gam, a.igm1, f, VS);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) sFt[v][tj][ti] = f[v];
-      }
-      if (tid < TT) {
-        R f[NV];
-        lds_face<R, 1, FLUX, LIM>(&sW[0][tid + 2][TR], 1, a.gam, a.igm1, f, VS);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) sFr[v][tid][TR] = f[v];
-      }
-      for (int q = tid - 64; q >= 0 && q < TR; q += NT - 64) {
-        R f[NV];
-        lds_face<R, 2, FLUX, LIM>(&sW[0][TT][q + 2], WR, a.gam, a.igm1, f, VS);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) sFt[v][TT][q] = f[v];
-      }
-    }
-    // phi face k+1/2 from the register ring (and the next plane's load)
-    R fhi[NV];
-    {
-      R wd[NV], wl[NV], wr[NV];
-      load_cons_prim<R, true>(a, (long long)wrap_phi(k + 2, np) * plane_cells + colbase, wd);
-      reconstruct<R, LIM, true>(wa, wb, wc, wd, wl, wr);
-      face_flux<R, 3, FLUX, true>(wl, wr, a.gam, a.igm1, fhi);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        wa[v] = wb[v];
-        wb[v] = wc[v];
-        wc[v] = wd[v];
-      }
-    }
-    // now wa = W(k), wb = W(k+1), wc = W(k+2)
-    if (body) {
-      __syncthreads();  // r / theta face fluxes are in LDS
-      if (valid) {
-        const R rm2 = a.m.rm2[ic], rp2 = a.m.rp2[ic], ivr = a.m.ivr[ic], hr = a.m.hr[ic];
-        const R sm = a.m.sm[jc], sp = a.m.sp[jc], ict = a.m.ict[jc];
-        const R fph = hr * a.m.phf[jc];
-        R L[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) {
-          L[v] = R(0);
-          L[v] -= (rp2 * sFr[v][tj][ti + 1] - rm2 * sFr[v][tj][ti]) * ivr;
-          L[v] -= hr * (sp * sFt[v][tj + 1][ti] - sm * sFt[v][tj][ti]) * ict;
-          L[v] -= fph * (fhi[v] - fcar[v]);
-        }
-        add_sources<R>(wa, a.m, ic, jc, a.omega, a.gravity, a.corot, L);
-        const R dt = (R)a.clock->dt;
-        const long long c = kbase + colbase;
-        R uc[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) uc[v] = a.uin[v * a.ncell + c];
-        if (STAGE == 1) {
-#pragma unroll
-          for (int v = 0; v < NV; ++v) a.uout[v * a.ncell + c] = uc[v] + dt * L[v];
-        } else {
-          R un[NV], unew[NV], wn[NV];
-#pragma unroll
-          for (int v = 0; v < NV; ++v) {
-            un[v] = a.un[v * a.ncell + c];
-            unew[v] = R(0.5) * un[v] + R(0.5) * (uc[v] + dt * L[v]);
-            a.uout[v * a.ncell + c] = unew[v];
-          }
-          cons2prim<R, true>(unew, wn, a.gm1);
-          lam = fmax(lam, cell_rate<R, true>(wn, a.m, ic, jc, a.gam));
-          const double d = (double)unew[0] - (double)un[0];
-          s1 += d * d;
-          s0 += (double)un[0] * (double)un[0];
-          if (bad == BAD_NONE && !cell_valid<R>(unew, wn)) bad = (int)c;
-        }
-      }
-    }
-#pragma unroll
-    for (int v = 0; v < NV; ++v) fcar[v] = fhi[v];
-  }
-  if (STAGE == 2) write_partials(a.partials, lam, s1, s0, bad);
+  const int tile = xcd_tile(b, nb);
+  __shared__ StageSmem<R, TR, TT> sm;
+  stage_tile<R, TR, TT, FLUX, LIM, STAGE>(a, kplanes, tile % nbx, (tile / nbx) % nby,
+                                          tile / (nbx * nby), tile, sm);
 }
 
 template <typename R, int TR, int TT, int FLUX, int LIM>
@@ -266,63 +69,13 @@ long long stage_lds_blocks(int nr, int nt, int np, int tile_r, int kplanes) {
          ((np + kplanes - 1) / kplanes);
 }
 
-// ------------------------------------------------------------ finalize --
-// Reduce the stage-2 (or CFL) block partials in a fixed order, advance the
-// clock, set the next dt; then, if probes are logged, append a record.
 template <typename R>
 __global__ void __launch_bounds__(256) k_finalize(DevClock* ck, const double* __restrict__ part,
                                                   int nblocks, double cfl, int advance,
                                                   int log_on, ProbeArgs pa,
                                                   const R* __restrict__ u,
                                                   double* __restrict__ log) {
-  __shared__ double sh[4][4];
-  __shared__ int s_rec;
-  __shared__ long long s_row, s_idx;
-  __shared__ double s_t;
-  const int tid = threadIdx.x;
-  if (!ck->active && advance) return;  // the stage kernels did not run
-  double l = 0.0, a1 = 0.0, a0 = 0.0;
-  int b = BAD_NONE;
-  for (int q = tid; q < nblocks; q += blockDim.x) {
-    l = fmax(l, part[4 * q + 0]);
-    a1 += part[4 * q + 1];
-    a0 += part[4 * q + 2];
-    const int qb = (int)part[4 * q + 3];
-    b = qb < b ? qb : b;
-  }
-  block_reduce(l, a1, a0, b, sh);
-  if (tid == 0) {
-    if (advance) {
-      ck->t = ck->clip ? ck->t_end : ck->t + ck->dt;
-      ck->step += 1;
-      ck->taken += 1;
-      ck->last_dt = ck->dt;
-      ck->resid = sqrt(a1) / sqrt(a0);
-      if (b != BAD_NONE) {
-        if (ck->bad == BAD_NONE || b < ck->bad) ck->bad = b;
-      }
-    }
-    set_next_dt(ck, cfl / l);
-    if (ck->bad != BAD_NONE) ck->active = 0;
-    // probe cadence decision on the new time
-    int rec = advance;
-    long long idx = 0;
-    if (rec && pa.cadence > 0.0) {
-      idx = (long long)floor(ck->t * pa.sc.t / pa.cadence);
-      rec = idx > ck->last_sample;
-    }
-    s_rec = log_on && rec;
-    s_row = ck->n_log;
-    s_idx = idx;
-    s_t = ck->t;
-    if (log_on && rec) {
-      ck->n_log += 1;
-      if (pa.cadence > 0.0) ck->last_sample = idx;
-    }
-  }
-  __syncthreads();
-  if (s_rec && s_row < pa.log_rows && tid < pa.n)
-    probe_eval<R>(pa, u, tid, s_t, log + (s_row * pa.max_probes + tid) * 12);
+  finalize_run<R>(ck, part, nblocks, cfl, advance, log_on, pa, u, log);
 }
 
 template <typename R>

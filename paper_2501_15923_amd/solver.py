@@ -18,6 +18,19 @@ def _np_ptr(a: np.ndarray):
     return a.ctypes.data_as(_abi.D)
 
 
+def make_grid(grid: Grid, max_maps=16, max_cmes=4, max_probes=8, max_traj_pts=1024,
+              probe_log_rows=0):
+    return _abi.IcrGrid(grid.nr, grid.nt, grid.np_, grid.r_in, grid.r_out, grid.th_min,
+                        grid.th_max, max_maps, max_cmes, max_probes, max_traj_pts,
+                        probe_log_rows)
+
+
+def make_phys(gamma=1.5, omega=OMEGA_SUN, cfl=0.4, flux=_abi.FLUX_TVDLF,
+              limiter=_abi.LIM_MINMOD, precision=64, gravity=True, corotation=True):
+    return _abi.IcrPhys(gamma, omega, cfl, flux, limiter, precision, int(gravity),
+                        int(corotation))
+
+
 class Solver:
     def __init__(self, grid: Grid, *, gamma=1.5, omega=OMEGA_SUN, cfl=0.4,
                  flux=_abi.FLUX_TVDLF, limiter=_abi.LIM_MINMOD, precision=64,
@@ -26,12 +39,10 @@ class Solver:
         import torch
         self.torch = torch
         self.grid = grid
+        self.owned = True
         self.device = torch.device("cuda", device)
-        self.g = _abi.IcrGrid(grid.nr, grid.nt, grid.np_, grid.r_in, grid.r_out, grid.th_min,
-                              grid.th_max, max_maps, max_cmes, max_probes, max_traj_pts,
-                              probe_log_rows)
-        self.p = _abi.IcrPhys(gamma, omega, cfl, flux, limiter, precision, int(gravity),
-                              int(corotation))
+        self.g = make_grid(grid, max_maps, max_cmes, max_probes, max_traj_pts, probe_log_rows)
+        self.p = make_phys(gamma, omega, cfl, flux, limiter, precision, gravity, corotation)
         nbytes = ctypes.c_size_t()
         check(lib().icr_workspace_bytes(ctypes.byref(self.g), ctypes.byref(self.p),
                                         ctypes.byref(nbytes)))
@@ -50,9 +61,20 @@ class Solver:
         self.h = h
         self.n_probes = 0
 
+    @classmethod
+    def wrap(cls, handle, grid: Grid):
+        """A view of a solver owned elsewhere (an ensemble run)."""
+        self = cls.__new__(cls)
+        self.grid = grid
+        self.owned = False
+        self.h = handle
+        self.n_probes = 0
+        return self
+
     def close(self):
         if getattr(self, "h", None):
-            lib().icr_destroy(self.h)
+            if self.owned:
+                lib().icr_destroy(self.h)
             self.h = None
 
     def __del__(self):
