@@ -39,11 +39,12 @@ __device__ bool grid_sync(GridBar* gb, unsigned nblocks, long long spin_limit) {
   if (threadIdx.x == 0 && threadIdx.y == 0) {
     ok = 1;
     const unsigned g = __hip_atomic_load(&gb->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    __threadfence();
+    // release this block's writes (L2 write-back), then arrive
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
     const unsigned arrived = atomicAdd(&gb->count, 1u);
     if (arrived == nblocks - 1) {
       __hip_atomic_store(&gb->count, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-      __threadfence();
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
       atomicAdd(&gb->gen, 1u);
     } else {
       long long n = 0;
@@ -57,7 +58,8 @@ __device__ bool grid_sync(GridBar* gb, unsigned nblocks, long long spin_limit) {
       }
     }
     if (__hip_atomic_load(&gb->error, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
-    __threadfence();
+    // acquire: later reads see every block's released writes
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   }
   __syncthreads();
   return ok != 0;
