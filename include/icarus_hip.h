@@ -217,6 +217,11 @@ int icr_sample_probes(icr_solver *s, double *out);
  * exceed cap; the log keeps the first probe_log_rows records). */
 int icr_read_probe_log(icr_solver *s, double *out, int cap, int *n_rec);
 
+/* Relaxation diagnostic: rho [kg/m^3] and v_r [m/s] on the sphere r_m for
+ * every (theta, phi) column, linear in r between the bracketing cell centres
+ * (clamped to the first / last centre): out [2][n_theta][n_phi] host. */
+int icr_sample_shell(icr_solver *s, double r_m, double *out);
+
 /* Inner-boundary primitive (SI) the solver would impose at time t_s, after
  * time interpolation and the CME overwrite: out [8][n_theta][n_phi] host. */
 int icr_boundary_at(icr_solver *s, double t_s, double *out);
@@ -279,10 +284,12 @@ int icr_ens_set_planes(icr_ensemble *e, int r, int planes);
 int icr_ens_set_mode(icr_ensemble *e, int persistent, int grid_blocks,
                      int use_graphs);
 
-/* Advance every run n_steps RK2 steps (each with its own dt).  info: NULL or
- * an array of n_runs results.  ICR_ERR_NONPHYSICAL if any run produced an
- * invalid cell (that run stops advancing, the others continue). */
-int icr_ens_step(icr_ensemble *e, int n_steps, icr_step_info *info);
+/* Advance every run up to n_steps RK2 steps (each with its own dt); if
+ * t_end_s > 0 each run's last step lands on t_end_s and runs at t_end_s stay
+ * put.  info: NULL or an array of n_runs results.  ICR_ERR_NONPHYSICAL if
+ * any run produced an invalid cell (that run stops advancing, the others
+ * continue). */
+int icr_ens_step(icr_ensemble *e, int n_steps, double t_end_s, icr_step_info *info);
 
 #ifdef __cplusplus
 }

@@ -42,6 +42,12 @@ class IcrStepInfo(ctypes.Structure):
                 ("last_dt", ctypes.c_double), ("residual", ctypes.c_double)]
 
 
+class NnShape(ctypes.Structure):
+    _fields_ = [("n_theta", ctypes.c_int), ("n_phi", ctypes.c_int), ("n_r", ctypes.c_int),
+                ("c1", ctypes.c_int), ("c2", ctypes.c_int), ("hidden", ctypes.c_int),
+                ("batch_max", ctypes.c_int)]
+
+
 class IcarusError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__(f"icarus error {code}: {msg}")
@@ -86,7 +92,26 @@ SIGNATURES = {
     "icr_ens_run": (I, [P, I, ctypes.POINTER(P)]),
     "icr_ens_set_planes": (I, [P, I, I]),
     "icr_ens_set_mode": (I, [P, I, I, I]),
-    "icr_ens_step": (I, [P, I, ctypes.POINTER(IcrStepInfo)]),
+    "icr_ens_step": (I, [P, I, ctypes.c_double, ctypes.POINTER(IcrStepInfo)]),
+    "icr_sample_shell": (I, [P, ctypes.c_double, D]),
+    # warm-start network (include/icarus_nn.h)
+    "icr_nn_last_error": (ctypes.c_char_p, []),
+    "icr_nn_param_count": (I, [ctypes.POINTER(NnShape), ctypes.POINTER(ctypes.c_longlong)]),
+    "icr_nn_workspace_bytes": (I, [ctypes.POINTER(NnShape), ctypes.POINTER(ctypes.c_size_t)]),
+    "icr_nn_create": (I, [ctypes.POINTER(NnShape), P, ctypes.c_size_t, P, ctypes.POINTER(P)]),
+    "icr_nn_destroy": (None, [P]),
+    "icr_nn_set_params": (I, [P, ctypes.POINTER(ctypes.c_float)]),
+    "icr_nn_get_params": (I, [P, ctypes.POINTER(ctypes.c_float)]),
+    "icr_nn_forward": (I, [P, I, P, P]),
+    "icr_nn_loss_grad": (I, [P, I, P, P, ctypes.POINTER(ctypes.c_double),
+                             ctypes.POINTER(ctypes.c_float)]),
+    "icr_nn_adam_step": (I, [P, ctypes.c_float, ctypes.c_float, ctypes.c_float, ctypes.c_float]),
+    "icr_nn_encode_map": (I, [P, I, D, D, ctypes.c_double, ctypes.c_double, P]),
+    "icr_nn_encode_target": (I, [P, D, D, D, D, ctypes.c_double, ctypes.c_double,
+                                 ctypes.c_double, P]),
+    "icr_nn_decode_state": (I, [P, D, P, D, D, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_double, D]),
+    "icr_nn_gemm_bf16": (I, [I, I, I, I, I, P, I, P, I, P, I, P, P]),
 }
 
 

@@ -12,7 +12,8 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 LIB = os.path.join(PKG, "libicarus_hip.so")
 SOURCES = [os.path.join(PKG, "csrc", f)
-           for f in ("icr_kernels.hip", "icr_stage_lds.hip", "icr_ensemble.hip", "icr_api.hip")]
+           for f in ("icr_kernels.hip", "icr_stage_lds.hip", "icr_ensemble.hip", "icr_api.hip",
+                     "icr_nn.hip")]
 HEADERS = [os.path.join(PKG, "csrc", f) for f in ("icr_kernels.hpp", "icr_device.hpp")] + \
     [os.path.join(ROOT, "include", "icarus_hip.h")]
 

@@ -792,6 +792,26 @@ int icr_boundary_at(icr_solver* s, double t_s, double* out) {
   return ICR_OK;
 }
 
+int icr_sample_shell(icr_solver* s, double r_m, double* out) {
+  if (!s || !out) return fail(ICR_ERR_ARG, "NULL argument");
+  if (!s->have_state) return fail(ICR_ERR_STATE, "no state yet");
+  if (!(r_m > 0.0)) return fail(ICR_ERR_ARG, "r must be > 0");
+  const int nt = s->g.n_theta, np = s->g.n_phi;
+  // the boundary-output buffer holds [8][nt][np] doubles; the shell needs [2][nt][np]
+  double* d = (double*)(s->ws + s->L.bout);
+  const double* rc = s->m64() + 8LL * s->g.n_r;
+  if (s->f32)
+    launch_shell<float>(s->u(s->cur), rc, s->g.n_r, nt, np, r_m / s->un.len, s->p.gamma,
+                        s->un.scale(), d, s->stream);
+  else
+    launch_shell<double>(s->u(s->cur), rc, s->g.n_r, nt, np, r_m / s->un.len, s->p.gamma,
+                         s->un.scale(), d, s->stream);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipMemcpyAsync(out, d, sizeof(double) * 2 * nt * np, hipMemcpyDeviceToHost, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  return ICR_OK;
+}
+
 int icr_profile_steps(icr_solver* s, int n, double* avg_ms) {
   if (!s || !avg_ms) return fail(ICR_ERR_ARG, "NULL argument");
   if (n < 1) return fail(ICR_ERR_ARG, "n_steps must be >= 1");
@@ -1085,7 +1105,7 @@ int icr_ens_set_mode(icr_ensemble* e, int persistent, int grid_blocks, int use_g
   return ICR_OK;
 }
 
-int icr_ens_step(icr_ensemble* e, int n_steps, icr_step_info* info) {
+int icr_ens_step(icr_ensemble* e, int n_steps, double t_end_s, icr_step_info* info) {
   if (!e) return fail(ICR_ERR_ARG, "ensemble is NULL");
   if (n_steps < 0) return fail(ICR_ERR_ARG, "n_steps must be >= 0");
   for (int r = 0; r < e->n; ++r) {
@@ -1096,7 +1116,8 @@ int icr_ens_step(icr_ensemble* e, int n_steps, icr_step_info* info) {
   if (rc) return rc;
   GridBar zero{};  // no ensemble kernel is in flight between calls
   HIP_TRY(hipMemcpyAsync(e->d_bar, &zero, sizeof zero, hipMemcpyHostToDevice, e->stream));
-  launch_ens_clock_begin(e->d_clocks, e->n, e->stream);
+  launch_ens_clock_begin(e->d_clocks, e->n, t_end_s > 0.0 ? t_end_s / e->runs[0]->un.t : -1.0,
+                         e->stream);
   // graphs replay an even chunk of steps; the parity in the tables is the
   // parity at the start of each replay
   constexpr int ECHUNK = 8;

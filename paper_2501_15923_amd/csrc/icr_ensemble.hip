@@ -134,11 +134,11 @@ __global__ void __launch_bounds__(256) k_ens_fin(const RunDesc<R>* __restrict__ 
   for_items(e.n_runs, [&](int r) { fin_item<R>(runs, r); });
 }
 
-__global__ void k_ens_clock_begin(DevClock* const* __restrict__ clocks, int n) {
+__global__ void k_ens_clock_begin(DevClock* const* __restrict__ clocks, int n, double t_end) {
   const int r = blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
   DevClock* ck = clocks[r];
-  ck->t_end = -1.0;
+  ck->t_end = t_end;
   ck->taken = 0;
   ck->active = ck->bad == BAD_NONE ? 1 : 0;
   set_next_dt(ck, ck->dt_cfl);
@@ -183,8 +183,8 @@ void launch_ensemble(const EnsLaunch& L, bool f32, hipStream_t s) {
   else ens_dispatch<double>(L, s);
 }
 
-void launch_ens_clock_begin(DevClock* const* clocks, int n, hipStream_t s) {
-  hipLaunchKernelGGL(k_ens_clock_begin, dim3((n + 63) / 64), dim3(64), 0, s, clocks, n);
+void launch_ens_clock_begin(DevClock* const* clocks, int n, double t_end, hipStream_t s) {
+  hipLaunchKernelGGL(k_ens_clock_begin, dim3((n + 63) / 64), dim3(64), 0, s, clocks, n, t_end);
 }
 
 void launch_ens_gather(DevClock* const* clocks, int n, DevClock* out, hipStream_t s) {

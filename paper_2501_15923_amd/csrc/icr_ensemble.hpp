@@ -44,7 +44,7 @@ struct EnsLaunch {
 };
 
 void launch_ensemble(const EnsLaunch& L, bool f32, hipStream_t s);
-void launch_ens_clock_begin(DevClock* const* clocks, int n, hipStream_t s);
+void launch_ens_clock_begin(DevClock* const* clocks, int n, double t_end, hipStream_t s);
 void launch_ens_gather(DevClock* const* clocks, int n, DevClock* out, hipStream_t s);
 int ensemble_blocks_per_cu(bool f32, int flux, int lim);
 

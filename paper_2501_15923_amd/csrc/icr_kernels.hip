@@ -412,6 +412,57 @@ template void launch_export<float>(const void*, double*, long long, int, const S
                                    hipStream_t);
 
 // ---------------------------------------------------------------- probes --
+// Primitive rho and v_r on the sphere r (code units) for every (theta, phi)
+// column, linear in r between the two bracketing cell centres (clamped to the
+// first / last centre): out [2][nt][np], SI.
+template <typename R>
+__global__ void k_shell(const R* __restrict__ u, const double* __restrict__ rc, int nr, int nt,
+                        int np, double r, double gam, Scale sc, double* __restrict__ out) {
+  const int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= nt * np) return;
+  const int j = q / np, k = q % np;
+  int i = 0;
+  double a = 0.0;
+  if (nr > 1 && r > rc[0]) {
+    if (r >= rc[nr - 1]) {
+      i = nr - 2;
+      a = 1.0;
+    } else {
+      int lo = 0, hi = nr - 1;
+      while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (rc[mid] <= r) lo = mid; else hi = mid;
+      }
+      i = lo;
+      a = (r - rc[i]) / (rc[i + 1] - rc[i]);
+    }
+  }
+  const long long n = (long long)nr * nt * np;
+  double res[2] = {0.0, 0.0};
+  for (int c = 0; c < (nr > 1 ? 2 : 1); ++c) {
+    const long long cell = ((long long)k * nt + j) * nr + i + c;
+    double uu[NV], w[NV];
+    for (int v = 0; v < NV; ++v) uu[v] = (double)u[v * n + cell];
+    cons2prim<double>(uu, w, gam - 1.0);
+    const double wt = c ? a : 1.0 - a;
+    res[0] += wt * w[0];
+    res[1] += wt * w[1];
+  }
+  out[q] = res[0] * sc.s[0];
+  out[nt * np + q] = res[1] * sc.s[1];
+}
+
+template <typename R>
+void launch_shell(const void* u, const double* rc, int nr, int nt, int np, double r, double gam,
+                  const Scale& sc, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_shell<R>, dim3((nt * np + 255) / 256), dim3(256), 0, s, (const R*)u, rc,
+                     nr, nt, np, r, gam, sc, out);
+}
+template void launch_shell<double>(const void*, const double*, int, int, int, double, double,
+                                   const Scale&, double*, hipStream_t);
+template void launch_shell<float>(const void*, const double*, int, int, int, double, double,
+                                  const Scale&, double*, hipStream_t);
+
 template <typename R>
 __global__ void k_probe_sample(ProbeArgs a, const DevClock* __restrict__ ck,
                                const R* __restrict__ u, double* __restrict__ out) {

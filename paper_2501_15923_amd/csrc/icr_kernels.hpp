@@ -302,6 +302,9 @@ template <typename R>
 void launch_probe_sample(const ProbeArgs& a, const DevClock* ck, const void* u, double* out,
                          hipStream_t s);
 template <typename R>
+void launch_shell(const void* u, const double* rc, int nr, int nt, int np, double r, double gam,
+                  const Scale& sc, double* out, hipStream_t s);
+template <typename R>
 void launch_stage_lds(const StageArgs<R>& a, int stage, int flux, int lim, int tile_r,
                       int kplanes, hipStream_t s);
 long long stage_lds_blocks(int nr, int nt, int np, int tile_r, int kplanes);

@@ -59,8 +59,8 @@ class Ensemble:
     def set_mode(self, persistent=1, grid_blocks=0, use_graphs=1):
         check(lib().icr_ens_set_mode(self.h, int(persistent), int(grid_blocks), int(use_graphs)))
 
-    def step(self, n):
+    def step(self, n, t_end=-1.0):
         infos = (_abi.IcrStepInfo * len(self.runs))()
-        check(lib().icr_ens_step(self.h, int(n), infos))
+        check(lib().icr_ens_step(self.h, int(n), float(t_end), infos))
         return [dict(steps=i.steps_taken, status=i.status, t=i.t, dt=i.last_dt,
                      resid=i.residual) for i in infos]

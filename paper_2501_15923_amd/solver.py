@@ -120,6 +120,13 @@ class Solver:
         check(lib().icr_get_state(self.h, _np_ptr(out), kind, 0))
         return out
 
+    def get_state_device(self, kind=_abi.STATE_PRIM_SI):
+        """The state as a torch float64 tensor on the device."""
+        import torch
+        out = torch.empty(self.shape, dtype=torch.float64, device="cuda")
+        check(lib().icr_get_state(self.h, _abi.dptr(out.data_ptr()), kind, 1))
+        return out
+
     def clock(self):
         c = _abi.IcrClock()
         check(lib().icr_get_clock(self.h, ctypes.byref(c)))
@@ -156,6 +163,12 @@ class Solver:
         n = ctypes.c_int()
         check(lib().icr_read_probe_log(self.h, _np_ptr(out), cap, ctypes.byref(n)))
         return out[:min(n.value, cap)], n.value
+
+    def shell(self, r):
+        """rho and v_r on the sphere of radius r [m]: [2][n_theta][n_phi]."""
+        out = np.zeros((2, self.grid.nt, self.grid.np_))
+        check(lib().icr_sample_shell(self.h, float(r), _np_ptr(out)))
+        return out
 
     def boundary_at(self, t):
         out = np.zeros((8, self.grid.nt, self.grid.np_))

@@ -112,6 +112,16 @@ def static_map(g: Grid, seed: int, tilt: float = 20 * DEG,
     return wind_map(g, tilt, phi0, omega=omega)
 
 
+def relax_map(g: Grid, seed: int, omega: float = OMEGA_SUN) -> np.ndarray:
+    """Static map for relaxation studies: tilt ~ U[0, 40] deg, slow-band
+    half-width 15 deg * U[0.8, 1.2], sheet phase ~ U[0, 2 pi)."""
+    rng = np.random.default_rng(seed)
+    tilt = rng.uniform(0.0, 40.0) * DEG
+    hw = 15.0 * DEG * rng.uniform(0.8, 1.2)
+    phi0 = rng.uniform(0.0, 2.0 * math.pi)
+    return wind_map(g, tilt, phi0, half_width=hw, omega=omega)
+
+
 def dynamic_maps(g: Grid, seed: int, n_maps: int = 10, cadence: float = 6 * HOUR,
                  tilt_max: float = 40 * DEG, width_var: float = 0.2,
                  omega: float = OMEGA_SUN):

@@ -1,0 +1,233 @@
+"""Learned warm start of the relaxation phase.
+
+Pipeline (all numerics on the GPU through libicarus_hip.so):
+  1. dataset: static boundary maps (synth.relax_map, training and held-out
+     seeds) relaxed plainly for two slow-wind crossing times by the batched
+     ensemble; the relaxed states become network targets (icr_nn_encode_target);
+  2. training: the network of include/icarus_nn.h with its own BF16-MFMA
+     forward/backward kernels and Adam (FP32 masters);
+  3. evaluation on held-out maps: steps and wall time to reach the relaxed
+     wind (relax.py criteria) from the radial expansion (plain) and from the
+     network's prediction (warm), plus the untrained network and the
+     mean-target predictor as ablations.
+
+    python -m paper_2501_15923_amd.warmstart --out WEIGHTS.npz --report REPORT.json
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import sys
+import time
+
+import numpy as np
+
+from . import relax, synth
+from .synth import AU, Grid
+
+TRAIN_SEED0, TEST_SEED0 = 1000, 2000
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def grid_geometry(solver):
+    """Cell-centre radii [m] and colatitudes of a solver (device tensors)."""
+    import torch
+    r, t, _ = solver.edges()
+    rc = 0.5 * (r[1:] + r[:-1])
+    thc = 0.5 * (t[1:] + t[:-1])
+    return torch.from_numpy(rc).cuda(), torch.from_numpy(thc).cuda()
+
+
+def relaxed_states(grid, seeds, t_ref, precision=64, batch=64, chunk=4000):
+    """Relax each seed's map for t_ref with the ensemble; yields
+    (seed, map, primitive SI state as a device tensor)."""
+    from .ensemble import Ensemble
+    for b0 in range(0, len(seeds), batch):
+        sub = seeds[b0:b0 + batch]
+        e = Ensemble([grid] * len(sub), precision=precision)
+        maps = [synth.relax_map(grid, s) for s in sub]
+        for m, run in zip(maps, e.runs):
+            run.set_maps(np.zeros(1), m[None])
+            run.init_radial()
+        t0 = time.perf_counter()
+        while True:
+            info = e.step(chunk, t_end=t_ref)
+            if max(i["steps"] for i in info) < chunk:
+                break
+        log(f"warmstart: relaxed {len(sub)} maps to {t_ref / 86400:.1f} d in "
+            f"{time.perf_counter() - t0:.1f} s")
+        for s, m, run in zip(sub, maps, e.runs):
+            yield s, m, run.get_state_device()
+        e.close()
+
+
+def build_dataset(net, grid, seeds, t_ref, rc, thc, precision=64):
+    import torch
+    n = len(seeds)
+    X = torch.empty((n, grid.nt, grid.np_, 8), dtype=torch.float32, device="cuda")
+    T = torch.empty((n, grid.nt * grid.np_, 8 * grid.nr), dtype=torch.float32, device="cuda")
+    M = torch.empty((n, 8, grid.nt, grid.np_), dtype=torch.float64, device="cuda")
+    for q, (s, m, st) in enumerate(relaxed_states(grid, seeds, t_ref, precision)):
+        dm = torch.from_numpy(m).cuda()
+        M[q] = dm
+        X[q] = net.encode_map(dm[None].contiguous(), thc, synth.OMEGA_SUN, grid.r_in)[0]
+        net.encode_target(dm, st, rc, thc, synth.OMEGA_SUN, grid.r_in, out=T[q])
+    return X, T, M
+
+
+def train(net, X, T, epochs=30, batch=8, lr=2e-3, seed=0):
+    import torch
+    n = X.shape[0]
+    rng = np.random.default_rng(seed)
+    steps = epochs * (n // batch)
+    hist = []
+    k = 0
+    t0 = time.perf_counter()
+    for ep in range(epochs):
+        perm = rng.permutation(n)
+        tot = 0.0
+        for b in range(n // batch):
+            idx = torch.from_numpy(perm[b * batch:(b + 1) * batch]).cuda()
+            x = X[idx].contiguous()
+            t = T[idx].reshape(batch * T.shape[1], T.shape[2]).contiguous()
+            loss = net.loss_grad(x, t)
+            cur = lr * 0.5 * (1.0 + math.cos(math.pi * k / steps))
+            net.adam_step(cur)
+            tot += loss
+            k += 1
+        hist.append(tot / (n // batch))
+        log(f"warmstart: epoch {ep} loss {hist[-1]:.3e}")
+    torch.cuda.synchronize()
+    return hist, time.perf_counter() - t0
+
+
+def evaluate(net, grid, seeds, t_ref, predictors, chunk=100, precision=64):
+    """Plain vs warm relaxation on held-out maps.  predictors: name ->
+    function(X [1][nt][np][8]) -> y [ncol][no] device tensor."""
+    import torch
+
+    from .solver import Solver
+    rows = []
+    for s in seeds:
+        m = synth.relax_map(grid, s)
+        solver = Solver(grid, precision=precision)
+        solver.set_maps(np.zeros(1), m[None])
+        solver.init_radial()
+        rc, thc = grid_geometry(solver)
+        plain = relax.plain_with_reference(solver, t_ref, chunk)
+        row = dict(seed=s, plain=dict((k, v) for k, v in plain.items() if k != "ref"))
+        dm = torch.from_numpy(m).cuda()
+        for name, pred in predictors.items():
+            solver.set_clock(0.0, 0)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            x = net.encode_map(dm[None].contiguous(), thc, synth.OMEGA_SUN, grid.r_in)
+            y = pred(x)
+            st = net.decode_state(dm, y, rc, thc, synth.OMEGA_SUN, grid.r_in)
+            solver.set_state(st)
+            torch.cuda.synchronize()
+            w0 = time.perf_counter() - t0
+            res = relax.relax(solver, plain["ref"], t_ref, chunk, wall0=w0)
+            res["init_wall"] = w0
+            row[name] = res
+        solver.close()
+        rows.append(row)
+        log(f"warmstart: seed {s} plain {row['plain'].get('steps')} steps " +
+            " ".join(f"{k} {row[k]['steps']}" for k in predictors))
+    return rows
+
+
+def summarise(rows, names):
+    out = {}
+    ok = [r for r in rows if r["plain"]["converged"]]
+    for name in names:
+        good = [r for r in ok if r[name]["converged"]]
+        if not good:
+            out[name] = dict(converged=0)
+            continue
+        ratio_w = [r[name]["wall"] / r["plain"]["wall"] for r in good]
+        ratio_s = [r[name]["steps"] / r["plain"]["steps"] for r in good]
+        out[name] = dict(converged=len(good), of=len(ok),
+                         wall_ratio_median=float(np.median(ratio_w)),
+                         wall_ratio_mean=float(np.mean(ratio_w)),
+                         steps_ratio_median=float(np.median(ratio_s)),
+                         plain_steps_median=float(np.median([r["plain"]["steps"] for r in good])),
+                         steps_median=float(np.median([r[name]["steps"] for r in good])),
+                         err_rho_median=float(np.median([r[name]["err_rho"] for r in good])),
+                         err_vr_median=float(np.median([r[name]["err_vr"] for r in good])))
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--nr", type=int, default=150)
+    ap.add_argument("--nt", type=int, default=30)
+    ap.add_argument("--nph", type=int, default=60)
+    ap.add_argument("--train", type=int, default=512)
+    ap.add_argument("--test", type=int, default=32)
+    ap.add_argument("--epochs", type=int, default=30)
+    ap.add_argument("--c1", type=int, default=64)
+    ap.add_argument("--c2", type=int, default=128)
+    ap.add_argument("--hidden", type=int, default=384)
+    ap.add_argument("--crossings", type=float, default=2.0)
+    ap.add_argument("--data-precision", type=int, default=32)
+    ap.add_argument("--out", default=None)
+    ap.add_argument("--weights", default=None, help="evaluate these weights (skip training)")
+    ap.add_argument("--report", default=None)
+    args = ap.parse_args(argv)
+    import torch
+
+    from .nn import WarmStartNet, init_params
+    from .solver import Solver
+    g = Grid(args.nr, args.nt, args.nph)
+    t_ref = args.crossings * relax.slow_crossing_time(g)
+    net = WarmStartNet(g.nt, g.np_, g.nr, args.c1, args.c2, args.hidden, batch_max=8)
+    p0 = init_params(*net.dims, seed=0)
+    probe = Solver(g)
+    rc, thc = grid_geometry(probe)
+    probe.close()
+    report = dict(grid=[g.nr, g.nt, g.np_], t_ref_days=t_ref / 86400, params=int(net.nparam))
+    if args.weights:
+        p = np.load(args.weights)["params"]
+        mean_t = torch.from_numpy(np.load(args.weights)["mean_target"]).cuda()
+    else:
+        train_seeds = list(range(TRAIN_SEED0, TRAIN_SEED0 + args.train))
+        t0 = time.perf_counter()
+        X, T, _ = build_dataset(net, g, train_seeds, t_ref, rc, thc, args.data_precision)
+        report["dataset_seconds"] = time.perf_counter() - t0
+        mean_t = T.mean(dim=0)
+        net.set_params(p0)
+        hist, tsec = train(net, X, T, args.epochs)
+        report.update(train_loss=hist, train_seconds=tsec)
+        p = net.get_params()
+        if args.out:
+            np.savez(args.out, params=p, mean_target=mean_t.cpu().numpy(),
+                     dims=np.array(net.dims))
+        del X, T
+        torch.cuda.empty_cache()
+    preds = {}
+
+    def with_params(params):
+        def f(x):
+            net.set_params(params)
+            return net.forward(x)
+        return f
+    preds["warm"] = with_params(p)
+    preds["untrained"] = with_params(p0)
+    preds["mean_target"] = lambda x: mean_t
+    test_seeds = list(range(TEST_SEED0, TEST_SEED0 + args.test))
+    rows = evaluate(net, g, test_seeds, t_ref, preds)
+    report["summary"] = summarise(rows, list(preds))
+    report["rows"] = rows
+    log(json.dumps(report["summary"], indent=1))
+    if args.report:
+        json.dump(report, open(args.report, "w"), indent=1, default=float)
+    return report
+
+
+if __name__ == "__main__":
+    main()

@@ -8,13 +8,15 @@ import re
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
-HEADER = os.path.join(ROOT, "include", "icarus_hip.h")
+HEADERS = [os.path.join(ROOT, "include", h) for h in ("icarus_hip.h", "icarus_nn.h")]
 
 
 def declared():
-    txt = open(HEADER).read()
-    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
-    return sorted(set(re.findall(r"\b(icr_[a-z_0-9]+)\s*\(", txt)))
+    names = set()
+    for h in HEADERS:
+        txt = re.sub(r"/\*.*?\*/", "", open(h).read(), flags=re.S)
+        names |= set(re.findall(r"\b(icr_[a-z_0-9]+)\s*\(", txt))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")

@@ -1,0 +1,128 @@
+"""Warm-start network kernels on the GPU against the NN oracle: the BF16
+MFMA product in every operand layout, the forward pass, the gradients
+(cosine >= 0.9999, relative L2 <= 1e-2 against the oracle with the same
+bfloat16 rounding), Adam, and the feature/target transforms."""
+import numpy as np
+import pytest
+
+from oracle import nn_oracle as no
+from paper_2501_15923_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def torch():
+    import torch
+    assert torch.cuda.is_available()
+    from paper_2501_15923_amd import _abi
+    _abi.lib()
+    return torch
+
+
+def bf16_bits(a):
+    f = np.asarray(a, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+    return u
+
+
+@pytest.mark.parametrize("ta,tb", [(0, 0), (0, 1), (1, 0), (1, 1)])
+@pytest.mark.parametrize("M,N,K", [(37, 53, 29), (130, 260, 72), (256, 128, 96), (5, 300, 600)])
+def test_gemm_bf16_layouts(torch, ta, tb, M, N, K):
+    from paper_2501_15923_amd.nn import gemm_bf16
+    rng = np.random.default_rng(M * 7 + N + K)
+    A = rng.normal(size=(M, K))
+    B = rng.normal(size=(K, N))
+    Ab, Bb = no.to_bf16(A), no.to_bf16(B)
+    As = Ab.T.copy() if ta else Ab
+    Bs = Bb.T.copy() if tb else Bb
+    a_dev = torch.from_numpy(bf16_bits(As).view(np.int16)).cuda()
+    b_dev = torch.from_numpy(bf16_bits(Bs).view(np.int16)).cuda()
+    bias = torch.from_numpy(rng.normal(size=N).astype(np.float32)).cuda()
+    C = gemm_bf16(ta, tb, a_dev, b_dev, M, N, K, As.shape[1], Bs.shape[1], bias).cpu().numpy()
+    ref = Ab @ Bb + bias.cpu().numpy()
+    assert np.max(np.abs(C - ref)) <= 1e-4 * np.max(np.abs(ref))
+
+
+SHAPE = dict(n_theta=6, n_phi=10, n_r=5, c1=8, c2=16, hidden=24)
+
+
+def small_net(torch, batch=2, seed=0):
+    from paper_2501_15923_amd.nn import WarmStartNet, init_params
+    net = WarmStartNet(**SHAPE, batch_max=batch)
+    p = init_params(*net.dims, seed=seed)
+    p[-8 * SHAPE["n_r"] - SHAPE["hidden"] * 8 * SHAPE["n_r"]:] *= 10  # non-trivial outputs
+    net.set_params(p)
+    sh = no.Shape(*net.dims)
+    return net, sh, p.astype(np.float64)
+
+
+def test_forward_matches_oracle(torch):
+    net, sh, p = small_net(torch)
+    rng = np.random.default_rng(7)
+    x = rng.normal(size=(2, 6, 10, 8))
+    y = net.forward(torch.from_numpy(x.astype(np.float32)).cuda()).cpu().numpy()
+    ref, _ = no.forward(sh, p.astype(np.float32).astype(np.float64), x.astype(np.float32))
+    assert np.linalg.norm(y - ref) / np.linalg.norm(ref) < 5e-3
+
+
+def test_gradients_match_oracle(torch):
+    net, sh, p = small_net(torch)
+    rng = np.random.default_rng(8)
+    x = rng.normal(size=(2, 6, 10, 8)).astype(np.float32)
+    t = rng.normal(0, 0.5, (2 * 60, sh.no)).astype(np.float32)
+    loss, g = net.loss_grad(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda(),
+                            want_grad=True)
+    lo, go = no.loss_grad(sh, p.astype(np.float32).astype(np.float64), x, t)
+    assert abs(loss - lo) / lo < 1e-3
+    cos = float(g @ go / (np.linalg.norm(g) * np.linalg.norm(go)))
+    rel = float(np.linalg.norm(g - go) / np.linalg.norm(go))
+    assert cos >= 0.9999 and rel <= 1e-2, (cos, rel)
+    # every parameter block individually
+    o = 0
+    for n in sh.sizes:
+        gb, ob = g[o:o + n], go[o:o + n]
+        assert np.linalg.norm(gb - ob) <= 2e-2 * np.linalg.norm(ob) + 1e-12
+        o += n
+
+
+def test_adam_step_and_training_decreases_loss(torch):
+    net, sh, p = small_net(torch)
+    rng = np.random.default_rng(9)
+    x = torch.from_numpy(rng.normal(size=(2, 6, 10, 8)).astype(np.float32)).cuda()
+    t = torch.from_numpy(rng.normal(0, 0.5, (2 * 60, sh.no)).astype(np.float32)).cuda()
+    _, g = net.loss_grad(x, t, want_grad=True)
+    net.adam_step(1e-3)
+    p1 = net.get_params()
+    # first Adam step with bias correction moves each weight by lr * g / (|g| + eps)
+    exp = p.astype(np.float32) - 1e-3 * g / (np.abs(g) + 1e-8)
+    assert np.allclose(p1, exp, rtol=1e-5, atol=1e-7)
+    l0 = net.loss_grad(x, t)
+    for _ in range(60):
+        net.loss_grad(x, t)
+        net.adam_step(3e-3)
+    assert net.loss_grad(x, t) < 0.5 * l0
+
+
+def test_transforms_match_oracle(torch):
+    from paper_2501_15923_amd.nn import WarmStartNet
+    g = synth.Grid(12, 6, 10)
+    net = WarmStartNet(g.nt, g.np_, g.nr, 8, 16, 24, batch_max=1)
+    th, _ = synth.angle_centres(g)
+    r = 0.1 * synth.AU * 20.0 ** (np.arange(g.nr + 1) / g.nr)
+    rc = 0.5 * (r[1:] + r[:-1])
+    m = synth.static_map(g, 4)
+    om, rin = synth.OMEGA_SUN, g.r_in
+    dm = torch.from_numpy(m[None].copy()).cuda()
+    dth = torch.from_numpy(th).cuda()
+    drc = torch.from_numpy(rc).cuda()
+    x = net.encode_map(dm, dth, om, rin).cpu().numpy()
+    assert np.allclose(x, no.encode_map(m[None], th, om, rin), rtol=1e-5, atol=1e-6)
+    rng = np.random.default_rng(6)
+    y = rng.normal(0, 0.2, (g.nt * g.np_, 8 * g.nr)).astype(np.float32)
+    st = net.decode_state(dm[0], torch.from_numpy(y).cuda(), drc, dth, om, rin).cpu().numpy()
+    ref = no.decode_state(m, y, rc, th, om, rin, 1.5)
+    assert np.allclose(st, ref, rtol=1e-12, atol=1e-30)
+    t = net.encode_target(dm[0], torch.from_numpy(ref).cuda(), drc, dth, om, rin).cpu().numpy()
+    assert np.allclose(t, no.encode_target(m, ref, rc, th, om, rin, 1.5), rtol=1e-5, atol=1e-6)

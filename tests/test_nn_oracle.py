@@ -1,0 +1,77 @@
+"""Pins for the NN oracle (CPU): its backward against central finite
+differences of its own FP64 forward, the 3x3 gather against its adjoint,
+bfloat16 rounding against exactly known values, and the feature / target
+transforms against their inverses and the radial-expansion laws."""
+import numpy as np
+
+from oracle import nn_oracle as no
+from paper_2501_15923_amd import synth
+
+
+def tiny():
+    sh = no.Shape(4, 6, 3, 4, 5, 6)
+    rng = np.random.default_rng(1)
+    p = rng.normal(0, 0.4, sh.nparam)
+    x = rng.normal(0, 1, (2, 4, 6, 8))
+    t = rng.normal(0, 0.3, (2 * 4 * 6, sh.no))
+    return sh, p, x, t
+
+
+def test_backward_matches_finite_differences():
+    sh, p, x, t = tiny()
+    loss, g = no.loss_grad(sh, p, x, t, bf16=False)
+    rng = np.random.default_rng(2)
+    idx = rng.choice(sh.nparam, 60, replace=False)
+    eps = 1e-6
+    for i in idx:
+        pp, pm = p.copy(), p.copy()
+        pp[i] += eps
+        pm[i] -= eps
+        fd = (no.loss_grad(sh, pp, x, t, bf16=False)[0] -
+              no.loss_grad(sh, pm, x, t, bf16=False)[0]) / (2 * eps)
+        assert abs(fd - g[i]) <= 1e-6 * max(1.0, abs(fd)) + 1e-9, (i, fd, g[i])
+
+
+def test_im2col_adjoint_and_boundaries():
+    rng = np.random.default_rng(3)
+    B, nt, nph, C = 2, 5, 7, 3
+    h = rng.normal(size=(B, nt, nph, C))
+    da = rng.normal(size=(B * nt * nph, 9 * C))
+    lhs = np.sum(no.im2col(h) * da)
+    rhs = np.sum(h * no.col2im(da, B, nt, nph, C))
+    assert abs(lhs - rhs) < 1e-10 * abs(lhs)
+    a = no.im2col(h).reshape(B, nt, nph, 9, C)
+    # periodic in phi, clamped in theta
+    assert np.array_equal(a[:, 2, 0, 1 * 3 + 0], h[:, 2, nph - 1])
+    assert np.array_equal(a[:, 0, 3, 0 * 3 + 1], h[:, 0, 3])
+    assert np.array_equal(a[:, nt - 1, 3, 2 * 3 + 1], h[:, nt - 1, 3])
+
+
+def test_bf16_rounding():
+    vals = np.array([1.0, 1.0 + 2 ** -8, 1.0 + 2 ** -7, 1.0 + 3 * 2 ** -9, -2.5, 3.0e38])
+    exp = np.array([1.0, 1.0, 1.0 + 2 ** -7, 1.0 + 2 ** -7, -2.5, 2.9999249e38])
+    got = no.to_bf16(vals)
+    assert np.allclose(got[:5], exp[:5], rtol=0, atol=0)
+    # ties to even: 1 + 2^-8 is halfway between 1 and 1 + 2^-7 -> 1
+    assert got[1] == 1.0
+
+
+def test_transforms_round_trip():
+    g = synth.Grid(12, 6, 10)
+    m = synth.static_map(g, 4)
+    th, _ = synth.angle_centres(g)
+    r = 0.1 * synth.AU * 20.0 ** (np.arange(g.nr + 1) / g.nr)
+    rc = 0.5 * (r[1:] + r[:-1])
+    om, rin = synth.OMEGA_SUN, g.r_in
+    base = no.radial_base(m, rc, th, om, rin, 1.5)
+    # the radial expansion itself has target zero
+    t0 = no.encode_target(m, base, rc, th, om, rin, 1.5)
+    assert np.max(np.abs(t0)) < 1e-12
+    rng = np.random.default_rng(5)
+    y = rng.normal(0, 0.2, t0.shape)
+    s = no.decode_state(m, y, rc, th, om, rin, 1.5)
+    assert np.allclose(no.encode_target(m, s, rc, th, om, rin, 1.5), y, atol=1e-10)
+    x = no.encode_map(m[None], th, om, rin)
+    # inertial v_phi of the map vanishes (plasma not rotating at r_in)
+    assert np.max(np.abs(x[..., 3])) < 1e-9
+    assert np.allclose(np.exp(x[..., 0]) * no.RHO0, np.transpose(m[0])[None].transpose(0, 2, 1))
