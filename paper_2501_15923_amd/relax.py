@@ -50,19 +50,29 @@ def plain_with_reference(solver, t_ref, chunk=100, r_shell=AU, tol_resid=1e-4, t
         if info["steps"] < chunk:
             break
     ref = hist[-1][3]
-    out = dict(ref=ref, t_ref=t_ref, total_steps=steps, total_wall=wall, converged=False)
+    rec = []
     for st, wl, res, sh in hist:
-        er, ev = shell_errors(sh, ref)
-        if res < tol_resid and max(er, ev) <= tol_shell:
-            out.update(converged=True, steps=st, wall=wl, resid=res, err_rho=er, err_vr=ev)
-            break
+        rec.append((st, wl, res) + shell_errors(sh, ref))
+    out = dict(ref=ref, t_ref=t_ref, total_steps=steps, total_wall=wall, history=rec)
+    out.update(first_relaxed(rec, tol_resid, tol_shell))
     return out
 
 
+def first_relaxed(rec, tol_resid, tol_shell):
+    """First (steps, wall, resid, err_rho, err_vr) record meeting both criteria."""
+    for st, wl, res, er, ev in rec:
+        if res < tol_resid and max(er, ev) <= tol_shell:
+            return dict(converged=True, steps=st, wall=wl, resid=res, err_rho=er, err_vr=ev)
+    st, wl, res, er, ev = rec[-1]
+    return dict(converged=False, steps=st, wall=wl, resid=res, err_rho=er, err_vr=ev)
+
+
 def relax(solver, ref_shell, t_max, chunk=100, r_shell=AU, tol_resid=1e-4, tol_shell=0.02,
-          wall0=0.0):
-    """Step from the current state until both criteria hold (or t_max)."""
+          wall0=0.0, max_steps=1 << 40):
+    """Step from the current state until both criteria hold (or t_max, or
+    max_steps); the record keeps (steps, wall, resid, err_rho, err_vr) per chunk."""
     steps, wall = 0, wall0
+    rec = []
     while True:
         _sync()
         t0 = time.perf_counter()
@@ -70,10 +80,8 @@ def relax(solver, ref_shell, t_max, chunk=100, r_shell=AU, tol_resid=1e-4, tol_s
         sh = solver.shell(r_shell)
         wall += time.perf_counter() - t0
         steps += info["steps"]
-        er, ev = shell_errors(sh, ref_shell)
-        if info["resid"] < tol_resid and max(er, ev) <= tol_shell:
-            return dict(converged=True, steps=steps, wall=wall, resid=info["resid"], err_rho=er,
-                        err_vr=ev)
-        if info["steps"] < chunk:
-            return dict(converged=False, steps=steps, wall=wall, resid=info["resid"], err_rho=er,
-                        err_vr=ev)
+        rec.append((steps, wall, info["resid"]) + shell_errors(sh, ref_shell))
+        out = first_relaxed(rec[-1:], tol_resid, tol_shell)
+        if out["converged"] or info["steps"] < chunk or steps >= max_steps:
+            out["history"] = rec
+            return out

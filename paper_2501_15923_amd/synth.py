@@ -57,14 +57,16 @@ def angle_centres(g: Grid):
 
 def wind_map(g: Grid, tilt: float, phi0: float, half_width: float = 15 * DEG,
              transition: float = 5 * DEG, v_slow: float = 350e3,
-             v_fast: float = 700e3, n_slow: float = 300e6, temp: float = 1e6,
-             b_r: float = 250e-9, omega: float = OMEGA_SUN) -> np.ndarray:
+             v_fast: float = 700e3, n_fast: float = 300e6, temp: float = 1e6,
+             b_r: float = 150e-9, omega: float = OMEGA_SUN) -> np.ndarray:
     """Bimodal wind around a tilted current sheet.
 
     The sheet is the great circle normal to n = (sin a cos p0, sin a sin p0,
     cos a); d = asin(x.n) is the signed angular distance to it.  Slow wind
     (v_slow) within +-half_width of the sheet, fast wind outside, joined by
-    a tanh of the given width; density such that rho v_r^2 is constant;
+    a tanh of the given width; density n_fast (v_fast / v_r)^2 (rho v_r^2
+    constant: 300 cm^-3 in the fast and 1200 cm^-3 in the slow wind by
+    default, the plasma beta at 0.1 AU staying above ~0.3);
     p = 2 n k_B T (fully ionised hydrogen); B_r = +b_r where d >= 0 and -b_r
     elsewhere; the transverse field and velocity follow the Parker relation
     at the inner radius (plasma not rotating in the inertial frame, field
@@ -79,7 +81,7 @@ def wind_map(g: Grid, tilt: float, phi0: float, half_width: float = 15 * DEG,
     d = np.arcsin(np.clip(dot, -1.0, 1.0))
     s = 0.5 * (1.0 + np.tanh((np.abs(d) - half_width) / transition))
     vr = v_slow + (v_fast - v_slow) * s
-    n = n_slow * (v_slow / vr) ** 2
+    n = n_fast * (v_fast / vr) ** 2
     out = np.zeros((8, g.nt, g.np_))
     out[0] = M_PROTON * n
     out[1] = vr
