@@ -46,10 +46,15 @@ def parse():
                     help="HBM traffic per stage-2 launch measured with rocprofv3 counters")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device-to-device copy of known size (counter calibration)")
-    ap.add_argument("--workload", default="prod", choices=("prod", "ensemble"),
+    ap.add_argument("--ingest-counters", nargs=4, default=None,
+                    metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
+                    help="write the --traffic file from four rocprofv3 --pmc output folders")
+    ap.add_argument("--workload", default="prod", choices=("prod", "ensemble", "relax"),
                     help="prod: 600x60x120 dynamic run (the headline line); ensemble: 64 "
                          "uneven runs in one persistent launch vs 64 sequential runs")
     ap.add_argument("--runs", type=int, default=64)
+    ap.add_argument("--maps", type=int, default=4, help="held-out maps for --workload relax")
+    ap.add_argument("--weights", default=WEIGHTS)
     return ap.parse_args()
 
 
@@ -123,6 +128,74 @@ def ensemble_bench(args):
     print(json.dumps(out), flush=True)
 
 
+WEIGHTS = os.path.join(ROOT, "paper_2501_15923_amd", "weights", "warmstart_150x30x60.npz")
+
+
+def relax_bench(args):
+    """Relaxation wall time to the steady wind on held-out static maps: the
+    plain start (radial expansion) against the warm start (network
+    prediction), FP64 solver, same convergence criteria; plus the network's
+    achieved BF16 TFLOP/s for a batch-8 forward and a training step."""
+    import numpy as np
+    import torch
+
+    from paper_2501_15923_amd import relax, synth, warmstart
+    from paper_2501_15923_amd.nn import WarmStartNet
+
+    z = np.load(args.weights)
+    dims = tuple(int(v) for v in z["dims"])
+    g = synth.Grid(dims[2], dims[0], dims[1])
+    net = WarmStartNet(*dims[:6], batch_max=8, phi_lo=dims[6], phi_hi=dims[7])
+    net.set_params(z["params"])
+    t_ref = 2.0 * relax.slow_crossing_time(g)
+    seeds = list(range(warmstart.TEST_SEED0, warmstart.TEST_SEED0 + args.maps))
+    log(f"bench: relaxation on {len(seeds)} held-out maps, grid {g.nr}x{g.nt}x{g.np_}")
+    rows = warmstart.evaluate(net, g, seeds, t_ref, {"warm": net.forward})
+    summ = warmstart.summarise(rows, ["warm"])["warm"]
+    # network throughput (BF16 MFMA products)
+    k1 = 3 * (dims[7] - dims[6] + 1) * 8
+    n_flop = 2 * g.nt * g.np_ * (k1 * dims[3] + 9 * dims[3] * dims[4] +
+                                 dims[4] * dims[5] + dims[5] * 8 * g.nr)
+    x = torch.randn(8, g.nt, g.np_, 8, device="cuda")
+    tg = torch.randn(8 * g.nt * g.np_, 8 * g.nr, device="cuda")
+    for _ in range(3):
+        net.forward(x)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    for _ in range(20):
+        net.forward(x)
+    ev1.record()
+    torch.cuda.synchronize()
+    fwd_ms = ev0.elapsed_time(ev1) / 20
+    ev0.record()
+    for _ in range(10):
+        net.loss_grad(x, tg)
+    ev1.record()
+    torch.cuda.synchronize()
+    train_ms = ev0.elapsed_time(ev1) / 10
+    out = {
+        "metric": "relaxation wall time, warm start / plain (median over held-out maps)",
+        "value": summ.get("wall_ratio_median"), "unit": "ratio", "n_gpus": 1,
+        "steps": int(summ.get("steps_median", 0)), "warmup": 0,
+        "ms_per_step": None, "higher_is_better": False, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64 solver, bf16 network", "data": "synthetic",
+        "config": {"workload": f"relax_static_{g.nr}x{g.nt}x{g.np_}", "maps": len(seeds),
+                   "criteria": "residual < 1e-4 and 1 AU rho, v_r within 2 % of the "
+                               "2-crossing-time reference", "chunk_steps": 50},
+        "relax": summ,
+        "per_map": [{"seed": r["seed"], "plain_steps": r["plain"].get("steps"),
+                     "plain_wall_s": r["plain"].get("wall"), "warm_steps": r["warm"]["steps"],
+                     "warm_wall_s": r["warm"]["wall"], "init_s": r["warm"]["init_wall"]}
+                    for r in rows],
+        "network": {"forward_batch8_ms": fwd_ms, "forward_tflops": 8 * n_flop / fwd_ms * 1e-9,
+                    "train_step_batch8_ms": train_ms,
+                    "train_tflops": 3 * 8 * n_flop / train_ms * 1e-9,
+                    "peak_bf16_tflops": 2500.0},
+    }
+    print(json.dumps(out), flush=True)
+
+
 def copy_calibration():
     """A plain device copy of 2 GiB, three times: the reference that scales
     the FETCH_SIZE / WRITE_SIZE counters to bytes."""
@@ -134,6 +207,41 @@ def copy_calibration():
         b.copy_(a)
     torch.cuda.synchronize()
     print(json.dumps({"copy_bytes": 8 * n, "launches": 3}), flush=True)
+
+
+def ingest_counters(dirs, precision, out_path):
+    """Turn four rocprofv3 --pmc runs (FETCH_SIZE and WRITE_SIZE of this
+    bench, then of --copy-calibration) into HBM bytes per stage-2 launch.
+    Each counter is scaled by what it reads for the 2 GiB copy."""
+    import csv
+    import glob
+
+    def rows(d):
+        f = glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True)
+        assert f, f"no counter_collection.csv under {d}"
+        return list(csv.DictReader(open(f[0])))
+
+    def copy_scale(d):
+        v = max(float(r["Counter_Value"]) for r in rows(d)
+                 if "copyBuffer" in r["Kernel_Name"])
+        return (1 << 31) / v  # bytes per counted unit
+
+    def stage2_mean(d):
+        v = [float(r["Counter_Value"]) for r in rows(d)
+             if "k_stage_lds" in r["Kernel_Name"] and r["Kernel_Name"].rstrip(")").split(
+                 "(")[0].endswith(", 2>")]
+        assert v, f"no stage-2 dispatches in {d}"
+        return sum(v) / len(v), len(v)
+
+    fetch, n_f = stage2_mean(dirs[0])
+    write, n_w = stage2_mean(dirs[1])
+    sf, sw = copy_scale(dirs[2]), copy_scale(dirs[3])
+    rec = {"precision": precision, "kernel_rev": kernel_rev(),
+           "fetch_bytes": fetch * sf, "write_bytes": write * sw,
+           "bytes_per_launch": fetch * sf + write * sw,
+           "fetch_scale": sf, "write_scale": sw, "dispatches": [n_f, n_w]}
+    json.dump(rec, open(out_path, "w"), indent=1)
+    print(json.dumps(rec), flush=True)
 
 
 def cpu_baseline(w, steps):
@@ -161,6 +269,9 @@ def main():
     if args.copy_calibration:
         copy_calibration()
         return
+    if args.ingest_counters:
+        ingest_counters(args.ingest_counters, args.precision, args.traffic)
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
               "sharding of this path is a design note, not a measured configuration.",
@@ -168,6 +279,9 @@ def main():
         sys.exit(2)
     if args.workload == "ensemble":
         ensemble_bench(args)
+        return
+    if args.workload == "relax":
+        relax_bench(args)
         return
     import numpy as np
     import torch
@@ -239,7 +353,7 @@ def kernel_rev():
     """Identifies the stage-kernel source the traffic counters were taken on."""
     import hashlib
     h = hashlib.sha1()
-    for f in ("icr_kernels.hip", "icr_stage_lds.hip", "icr_device.hpp", "icr_kernels.hpp"):
+    for f in ("icr_stage_lds.hip", "icr_stage_lds.hpp", "icr_device.hpp", "icr_kernels.hpp"):
         h.update(open(os.path.join(ROOT, "paper_2501_15923_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:12]
 

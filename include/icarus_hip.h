@@ -69,7 +69,9 @@ enum {
 
 /* Grid and capacities.  The radial edges are r_in * q^i, q = (r_out /
  * r_in)^(1/n_r) (radially stretched grid, Sect. 2); colatitude uniform on
- * [th_min, th_max]; longitude uniform and periodic on [0, 2 pi).  The
+ * [th_min, th_max] with reflecting edges (mirror rows, v_theta and B_theta
+ * negated; the paper does not state this boundary); longitude uniform and
+ * periodic on [0, 2 pi); zero-gradient outflow at r_out.  The
  * capacities size the workspace: boundary maps, cone CMEs, probes, points
  * per trajectory table and rows of the device probe log. */
 typedef struct {

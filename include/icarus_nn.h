@@ -9,18 +9,23 @@
  *
  * Network per sample, on the (theta, phi) grid of the map:
  *   features X [n_theta][n_phi][8]  (normalised boundary primitives)
- *   conv 3x3 8 -> c1, SiLU; conv 3x3 c1 -> c2, SiLU   (periodic in phi,
- *   edge-clamped in theta)
+ *   conv 3 x nk 8 -> c1, SiLU, over colatitude offsets -1..1 and longitude
+ *   offsets phi_lo..phi_hi (nk = phi_hi - phi_lo + 1): plasma at longitude
+ *   phi and radius r left the inner boundary at phi + Omega (r - r_in) / v_r
+ *   in the co-rotating frame, so a window reaching far to positive offsets
+ *   sees the footpoints of every radius;
+ *   conv 3x3 c1 -> c2, SiLU   (both periodic in phi, edge-clamped in theta)
  *   per (theta, phi) column: Linear c2 -> hidden, SiLU; Linear hidden -> n_r*8
  *   output Y [n_theta*n_phi][n_r][8]: normalised residual of the state over
  *   the radial expansion of the map (log-ratio for rho and p, offsets in
  *   units of 100 km/s for velocities, of |B_r|+|B_phi| of the expansion for B).
  * Products: BF16 operands on MFMA with FP32 accumulation.  Parameters: FP32
  * masters (updated by Adam) with BF16 copies used by the products.
- * Parameter vector order: W1 [72][c1], b1 [c1], W2 [9*c1][c2], b2 [c2],
+ * Parameter vector order: W1 [3*nk*8][c1], b1 [c1], W2 [9*c1][c2], b2 [c2],
  * W3 [c2][hidden], b3 [hidden], W4 [hidden][n_r*8], b4 [n_r*8]; weights
  * row-major [in][out]; conv input index = tap*C + channel with
- * tap = (dtheta+1)*3 + (dphi+1).
+ * tap = (dtheta+1)*nk + (dphi-phi_lo) (nk = 3, phi_lo = -1 in the second
+ * convolution).
  *
  * Conventions: as in icarus_hip.h (status codes, caller-owned 256-byte
  * aligned device workspace, work enqueued on the given HIP stream).  "dev"
@@ -41,6 +46,8 @@ typedef struct {
   int n_theta, n_phi, n_r;  /* grid of the solver the network serves      */
   int c1, c2, hidden;       /* encoder channels and decoder width         */
   int batch_max;            /* samples per forward/backward call          */
+  int phi_lo, phi_hi;       /* first-layer longitude offsets, inclusive:
+                               phi_lo <= 0 <= phi_hi, window <= n_phi     */
 } icr_nn_shape;
 
 typedef struct icr_nn icr_nn;

@@ -31,28 +31,29 @@ def silu_grad(z):
     return s * (1.0 + z * (1.0 - s))
 
 
-def im2col(h):
-    """h [B][nt][np][C] -> [B*nt*np][9*C], column index tap*C + c with
-    tap = (dj+1)*3 + (dk+1); theta clamped at the edges, phi periodic."""
+def im2col(h, dk0=-1, nk=3):
+    """h [B][nt][np][C] -> [B*nt*np][3*nk*C], column index tap*C + c with
+    tap = (dj+1)*nk + (dk-dk0), dj in -1..1, dk in dk0..dk0+nk-1; theta
+    clamped at the edges, phi periodic."""
     B, nt, nph, C = h.shape
-    out = np.zeros((B, nt, nph, 9, C))
+    out = np.zeros((B, nt, nph, 3 * nk, C))
     for dj in (-1, 0, 1):
         jj = np.clip(np.arange(nt) + dj, 0, nt - 1)
-        for dk in (-1, 0, 1):
+        for dk in range(dk0, dk0 + nk):
             kk = (np.arange(nph) + dk) % nph
-            out[:, :, :, (dj + 1) * 3 + (dk + 1), :] = h[:, jj][:, :, kk]
-    return out.reshape(B * nt * nph, 9 * C)
+            out[:, :, :, (dj + 1) * nk + (dk - dk0), :] = h[:, jj][:, :, kk]
+    return out.reshape(B * nt * nph, 3 * nk * C)
 
 
-def col2im(da, B, nt, nph, C):
+def col2im(da, B, nt, nph, C, dk0=-1, nk=3):
     """Adjoint of im2col."""
-    da = da.reshape(B, nt, nph, 9, C)
+    da = da.reshape(B, nt, nph, 3 * nk, C)
     dh = np.zeros((B, nt, nph, C))
     for dj in (-1, 0, 1):
         jj = np.clip(np.arange(nt) + dj, 0, nt - 1)
-        for dk in (-1, 0, 1):
+        for dk in range(dk0, dk0 + nk):
             kk = (np.arange(nph) + dk) % nph
-            tap = (dj + 1) * 3 + (dk + 1)
+            tap = (dj + 1) * nk + (dk - dk0)
             for j in range(nt):
                 for k in range(nph):
                     dh[:, jj[j], kk[k]] += da[:, j, k, tap, :]
@@ -60,11 +61,13 @@ def col2im(da, B, nt, nph, C):
 
 
 class Shape:
-    def __init__(self, n_theta, n_phi, n_r, c1, c2, hidden):
+    def __init__(self, n_theta, n_phi, n_r, c1, c2, hidden, phi_lo=-1, phi_hi=1):
         self.nt, self.np_, self.nr = n_theta, n_phi, n_r
         self.c1, self.c2, self.h = c1, c2, hidden
+        self.phi_lo, self.nk = phi_lo, phi_hi - phi_lo + 1
+        self.k1 = 3 * self.nk * 8
         self.no = 8 * n_r
-        self.sizes = [72 * c1, c1, 9 * c1 * c2, c2, c2 * hidden, hidden, hidden * self.no,
+        self.sizes = [self.k1 * c1, c1, 9 * c1 * c2, c2, c2 * hidden, hidden, hidden * self.no,
                       self.no]
 
     @property
@@ -73,7 +76,7 @@ class Shape:
 
     def unpack(self, p):
         out, o = [], 0
-        shapes = [(72, self.c1), (self.c1,), (9 * self.c1, self.c2), (self.c2,),
+        shapes = [(self.k1, self.c1), (self.c1,), (9 * self.c1, self.c2), (self.c2,),
                   (self.c2, self.h), (self.h,), (self.h, self.no), (self.no,)]
         for sh in shapes:
             n = int(np.prod(sh))
@@ -87,7 +90,7 @@ def forward(shape, params, x, bf16=True):
     r = to_bf16 if bf16 else (lambda a: np.asarray(a, dtype=np.float64))
     W1, b1, W2, b2, W3, b3, W4, b4 = shape.unpack(params)
     B = x.shape[0]
-    a1 = im2col(r(x))
+    a1 = im2col(r(x), shape.phi_lo, shape.nk)
     z1 = a1 @ r(W1) + b1
     h1 = r(silu(z1))
     a2 = im2col(h1.reshape(B, shape.nt, shape.np_, shape.c1))

@@ -16,6 +16,8 @@
  *     (Sect. 3), and cone-CME overwrite of only the points inside the cone
  *     (Sect. 3.2, bc_icarus);
  *   - the initial state by radial expansion of the first map (Sect. 2.1);
+ *   - edges the paper does not state: zero-gradient outflow at r_out,
+ *     reflecting colatitude edges, periodic longitude;
  *   - sampling of the solution at moving locations interpolated from
  *     trajectory tables on the radially stretched grid (Sect. 2).
  * The paper does not print the finite-volume scheme; the reading used here
@@ -486,14 +488,21 @@ static void fill_ghosts(orc_ctx *c, double *U, double t) {
         for (int j = 0; j < nt; ++j)
           for (int g = 0; g < NG; ++g)
             U[IX(c, v, nr + g, j, k)] = U[IX(c, v, nr - 1, j, k)];
-    /* colatitude edges: zero-gradient copy of all variables */
-    for (int v = 0; v < NV; ++v)
+    /* colatitude edges: reflecting.  Ghost layer g mirrors active row g-1
+     * from the edge (the last row when the grid has fewer rows) with the
+     * theta components of momentum and field negated, so that no mass,
+     * magnetic flux or energy crosses the edge. */
+    for (int v = 0; v < NV; ++v) {
+      double sgn = (v == 2 || v == 6) ? -1.0 : 1.0;
       for (int k = 0; k < np; ++k)
         for (int i = 0; i < nr; ++i)
           for (int g = 1; g <= NG; ++g) {
-            U[IX(c, v, i, -g, k)] = U[IX(c, v, i, 0, k)];
-            U[IX(c, v, i, nt - 1 + g, k)] = U[IX(c, v, i, nt - 1, k)];
+            int lo = g - 1 < nt ? g - 1 : nt - 1;
+            int hi = nt - g >= 0 ? nt - g : 0;
+            U[IX(c, v, i, -g, k)] = sgn * U[IX(c, v, i, lo, k)];
+            U[IX(c, v, i, nt - 1 + g, k)] = sgn * U[IX(c, v, i, hi, k)];
           }
+    }
   } else {
     for (int v = 0; v < NV; ++v)
       for (int k = 0; k < np; ++k)

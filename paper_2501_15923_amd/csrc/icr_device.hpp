@@ -46,6 +46,21 @@ struct Metric {
   R ilth;                                                 // 1 / dtheta
 };
 
+// Reflecting colatitude edges: a row index beyond [0, nt) reads the mirror
+// row (-1 - j below, 2 nt - 1 - j above, clamped to the grid) with the theta
+// components of velocity and field negated (flip = true).
+__device__ __forceinline__ int mirror_row(int j, int nt, bool& flip) {
+  flip = j < 0 || j >= nt;
+  const int m = j < 0 ? -1 - j : (j >= nt ? 2 * nt - 1 - j : j);
+  return m < 0 ? 0 : (m >= nt ? nt - 1 : m);
+}
+
+template <typename R>
+__device__ __forceinline__ void flip_theta(R (&w)[NV]) {
+  w[2] = -w[2];
+  w[6] = -w[6];
+}
+
 template <typename R>
 __device__ __forceinline__ R rmax(R a, R b) { return a > b ? a : b; }
 template <typename R>

@@ -201,15 +201,19 @@ __global__ void __launch_bounds__(256) k_stage_v1(StageArgs<R> a) {
         for (int v = 0; v < NV; ++v) L[v] -= (rp2 * fp[v] - rm2 * fm[v]) * ivr;
       }
       const R hr = a.m.hr[i];
-      {  // theta faces, zero-gradient copies beyond the colatitude edges
+      {  // theta faces, mirror rows beyond the (reflecting) colatitude edges
         R w0[NV], w1[NV], w3[NV], w4[NV], wl[NV], wr[NV], fm[NV], fp[NV];
-        const int jm2 = j - 2 < 0 ? 0 : j - 2, jm1 = j - 1 < 0 ? 0 : j - 1;
-        const int jp1 = j + 1 >= a.nt ? a.nt - 1 : j + 1;
-        const int jp2 = j + 2 >= a.nt ? a.nt - 1 : j + 2;
+        bool f0, f1, f3, f4;
+        const int jm2 = mirror_row(j - 2, a.nt, f0), jm1 = mirror_row(j - 1, a.nt, f1);
+        const int jp1 = mirror_row(j + 1, a.nt, f3), jp2 = mirror_row(j + 2, a.nt, f4);
         load_prim(a, i, jm2, k, w0);
         load_prim(a, i, jm1, k, w1);
         load_prim(a, i, jp1, k, w3);
         load_prim(a, i, jp2, k, w4);
+        if (f0) flip_theta(w0);
+        if (f1) flip_theta(w1);
+        if (f3) flip_theta(w3);
+        if (f4) flip_theta(w4);
         reconstruct<R, LIM>(w0, w1, wc, w3, wl, wr);
         face_flux<R, 2, FLUX>(wl, wr, a.gam, a.igm1, fm);
         reconstruct<R, LIM>(w1, wc, w3, w4, wl, wr);

@@ -3,7 +3,7 @@
 // the period of interest, Sect. 3).
 //
 // Network (per sample): boundary map features X [n_theta][n_phi][8]
-//   conv 3x3 (periodic in phi, edge-clamped in theta) 8 -> C1, SiLU
+//   conv 3 x (phi_hi - phi_lo + 1) (periodic in phi, edge-clamped in theta) 8 -> C1, SiLU
 //   conv 3x3 C1 -> C2, SiLU                              = latent z per column
 //   per-column decoder: Linear C2 -> H, SiLU; Linear H -> n_r * 8
 // output: normalised residual of the state over the radial expansion of the
@@ -163,31 +163,35 @@ __global__ void k_silu_back(const float* __restrict__ dh, const float* __restric
   }
 }
 
-// 3x3 neighbourhood gather: A[b, j, k][tap * C + c] = H[b, clamp(j + dj), (k + dk) mod np][c],
-// tap = (dj + 1) * 3 + (dk + 1)
+// neighbourhood gather over 3 colatitude rows and nk longitudes starting at offset dk0:
+// A[b, j, k][tap * C + c] = H[b, clamp(j + dj), (k + dk) mod np][c],
+// tap = (dj + 1) * nk + (dk - dk0), dj in {-1, 0, 1}, dk in [dk0, dk0 + nk)
 __global__ void k_im2col(const uint16_t* __restrict__ h, uint16_t* __restrict__ a, int B, int nt,
-                         int np, int C) {
-  const long long n = (long long)B * nt * np * 9 * C;
+                         int np, int C, int dk0, int nk) {
+  const int taps = 3 * nk;
+  const long long n = (long long)B * nt * np * taps * C;
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
   const int c = (int)(i % C);
   long long r = i / C;
-  const int tap = (int)(r % 9);
-  r /= 9;
+  const int tap = (int)(r % taps);
+  r /= taps;
   const int k = (int)(r % np);
   r /= np;
   const int j = (int)(r % nt);
   const int b = (int)(r / nt);
-  const int dj = tap / 3 - 1, dk = tap % 3 - 1;
+  const int dj = tap / nk - 1, dk = tap % nk + dk0;
   int jj = j + dj;
   jj = jj < 0 ? 0 : (jj >= nt ? nt - 1 : jj);
-  const int kk = (k + dk + np) % np;
+  int kk = (k + dk) % np;
+  if (kk < 0) kk += np;
   a[i] = h[(((long long)b * nt + jj) * np + kk) * C + c];
 }
 
 // adjoint of k_im2col: dH[b, j', k'][c] = sum of dA over every (j, k, tap) that gathered (j', k')
 __global__ void k_col2im(const float* __restrict__ da, float* __restrict__ dh, int B, int nt,
-                         int np, int C) {
+                         int np, int C, int dk0, int nk) {
+  const int taps = 3 * nk;
   const long long n = (long long)B * nt * np * C;
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -206,10 +210,11 @@ __global__ void k_col2im(const float* __restrict__ da, float* __restrict__ dh, i
     if (dj == -1 && j == 0) js[ns++] = 0;       // clamp(0 - 1) = 0
     if (dj == 1 && j == nt - 1) js[ns++] = nt - 1;  // clamp(nt - 1 + 1) = nt - 1
     for (int q = 0; q < ns; ++q)
-      for (int dk = -1; dk <= 1; ++dk) {
-        const int ks = (k - dk + np) % np;
-        const int tap = (dj + 1) * 3 + (dk + 1);
-        s += da[((((long long)b * nt + js[q]) * np + ks) * 9 + tap) * C + c];
+      for (int t = 0; t < nk; ++t) {
+        int ks = (k - (t + dk0)) % np;
+        if (ks < 0) ks += np;
+        const int tap = (dj + 1) * nk + t;
+        s += da[((((long long)b * nt + js[q]) * np + ks) * taps + tap) * C + c];
       }
   }
   dh[i] = s;
@@ -407,7 +412,7 @@ Sizes sizes(const icr_nn_shape& s) {
   z.c2 = s.c2;
   z.h = s.hidden;
   z.no = s.n_r * 8;
-  z.k1 = 9 * 8;
+  z.k1 = 3 * (s.phi_hi - s.phi_lo + 1) * 8;
   z.k2 = 9 * s.c1;
   z.w1 = (long long)z.k1 * z.c1;
   z.w2 = (long long)z.k2 * z.c2;
@@ -422,6 +427,8 @@ int check_shape(const icr_nn_shape* s) {
   if (s->n_theta < 1 || s->n_phi < 3 || s->n_r < 1 || s->c1 < 1 || s->c2 < 1 || s->hidden < 1 ||
       s->batch_max < 1)
     return nfail(ICR_NN_ERR_ARG, "invalid network shape");
+  if (s->phi_lo > 0 || s->phi_hi < 0 || s->phi_hi - s->phi_lo + 1 > s->n_phi)
+    return nfail(ICR_NN_ERR_ARG, "first-layer longitude window must hold offset 0 and fit n_phi");
   return ICR_NN_OK;
 }
 
@@ -525,10 +532,12 @@ void forward(icr_nn* n, int B, const float* x_dev) {
   const long long M = (long long)B * z.ncol;
   hipStream_t s = n->stream;
   hipLaunchKernelGGL(k_to_bf16, g1(M * 8), dim3(256), 0, s, x_dev, n->xb, M * 8);
-  hipLaunchKernelGGL(k_im2col, g1(M * z.k1), dim3(256), 0, s, n->xb, n->a1, B, nt, np, 8);
+  hipLaunchKernelGGL(k_im2col, g1(M * z.k1), dim3(256), 0, s, n->xb, n->a1, B, nt, np, 8,
+                     n->s.phi_lo, n->s.phi_hi - n->s.phi_lo + 1);
   gemm(0, 0, n->a1, n->W1b, n->z1, n->b1, (int)M, z.c1, z.k1, z.k1, z.c1, z.c1, s);
   hipLaunchKernelGGL(k_silu, g1(M * z.c1), dim3(256), 0, s, n->z1, n->h1, M * z.c1);
-  hipLaunchKernelGGL(k_im2col, g1(M * z.k2), dim3(256), 0, s, n->h1, n->a2, B, nt, np, z.c1);
+  hipLaunchKernelGGL(k_im2col, g1(M * z.k2), dim3(256), 0, s, n->h1, n->a2, B, nt, np, z.c1,
+                     -1, 3);
   gemm(0, 0, n->a2, n->W2b, n->z2, n->b2, (int)M, z.c2, z.k2, z.k2, z.c2, z.c2, s);
   hipLaunchKernelGGL(k_silu, g1(M * z.c2), dim3(256), 0, s, n->z2, n->h2, M * z.c2);
   gemm(0, 0, n->h2, n->W3b, n->z3, n->b3, (int)M, z.h, z.c2, z.c2, z.h, z.h, s);
@@ -560,7 +569,8 @@ void backward(icr_nn* n, int B, const float* t_dev) {
   gemm(1, 0, n->a2, n->dz2b, n->gW2, nullptr, z.k2, z.c2, (int)M, z.k2, z.c2, z.c2, s);
   hipLaunchKernelGGL(k_colsum, g1(z.c2), dim3(256), 0, s, n->dz2, n->gb2, (int)M, z.c2);
   gemm(0, 1, n->dz2b, n->W2b, n->da2, nullptr, (int)M, z.k2, z.c2, z.c2, z.c2, z.k2, s);
-  hipLaunchKernelGGL(k_col2im, g1(M * z.c1), dim3(256), 0, s, n->da2, n->dh1, B, nt, np, z.c1);
+  hipLaunchKernelGGL(k_col2im, g1(M * z.c1), dim3(256), 0, s, n->da2, n->dh1, B, nt, np, z.c1,
+                     -1, 3);
   hipLaunchKernelGGL(k_silu_back, g1(M * z.c1), dim3(256), 0, s, n->dh1, n->z1, n->dz1, n->dz1b,
                      M * z.c1);
   gemm(1, 0, n->a1, n->dz1b, n->gW1, nullptr, z.k1, z.c1, (int)M, z.k1, z.c1, z.c1, s);

@@ -79,6 +79,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R>& a, int kplanes, i
   const int ic = i < nr ? i : nr - 1, jc = j < nt ? j : nt - 1;
   const int active = a.clock->active;
   const long long colbase = (long long)jc * nr + ic;  // + k * nt * nr
+  // own-column loads: rows past the last colatitude mirror it (they serve
+  // as ghost rows of the last active row's upper theta face)
+  bool flipj;
+  const long long lbase = (long long)mirror_row(j, nt, flipj) * nr + ic;
   const long long plane_cells = (long long)nt * nr;
 
   if (!active) {
@@ -95,9 +99,14 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R>& a, int kplanes, i
   // wb = W(k), wc = W(k+1) and fcar = flux of face k-1/2.  Iteration k0-1
   // only forms fcar, through the same code as every later phi face.
   R wa[NV], wb[NV], wc[NV], fcar[NV];
-  load_cons_prim<R, true>(a, (long long)wrap_phi(k0 - 2, np) * plane_cells + colbase, wa);
-  load_cons_prim<R, true>(a, (long long)wrap_phi(k0 - 1, np) * plane_cells + colbase, wb);
-  load_cons_prim<R, true>(a, (long long)wrap_phi(k0, np) * plane_cells + colbase, wc);
+  load_cons_prim<R, true>(a, (long long)wrap_phi(k0 - 2, np) * plane_cells + lbase, wa);
+  load_cons_prim<R, true>(a, (long long)wrap_phi(k0 - 1, np) * plane_cells + lbase, wb);
+  load_cons_prim<R, true>(a, (long long)wrap_phi(k0, np) * plane_cells + lbase, wc);
+  if (flipj) {
+    flip_theta(wa);
+    flip_theta(wb);
+    flip_theta(wc);
+  }
 #pragma unroll
   for (int v = 0; v < NV; ++v) fcar[v] = R(0);
 
@@ -123,8 +132,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R>& a, int kplanes, i
           jj = q - s * TT;
           ii = s < 2 ? s - 2 : TR + s - 2;
         }
-        int gi = i0 + ii, gj = j0 + jj;
-        gj = gj < 0 ? 0 : (gj >= nt ? nt - 1 : gj);
+        int gi = i0 + ii;
+        bool flip;
+        const int gj = mirror_row(j0 + jj, nt, flip);
         R w[NV];
         if (gi < 0) {
           const long long g = (long long)k * nt + gj;
@@ -134,6 +144,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R>& a, int kplanes, i
           gi = gi >= nr ? nr - 1 : gi;
           load_cons_prim<R, true>(a, kbase + (long long)gj * nr + gi, w);
         }
+        if (flip) flip_theta(w);
 #pragma unroll
         for (int v = 0; v < NV; ++v) sW[v][jj + 2][ii + 2] = w[v];
       }
@@ -170,7 +181,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R>& a, int kplanes, i
     R fhi[NV];
     {
       R wd[NV], wl[NV], wr[NV];
-      load_cons_prim<R, true>(a, (long long)wrap_phi(k + 2, np) * plane_cells + colbase, wd);
+      load_cons_prim<R, true>(a, (long long)wrap_phi(k + 2, np) * plane_cells + lbase, wd);
+      if (flipj) flip_theta(wd);
       reconstruct<R, LIM, true>(wa, wb, wc, wd, wl, wr);
       face_flux<R, 3, FLUX, true>(wl, wr, a.gam, a.igm1, fhi);
 #pragma unroll

@@ -59,8 +59,13 @@ class Ensemble:
     def set_mode(self, persistent=1, grid_blocks=0, use_graphs=1):
         check(lib().icr_ens_set_mode(self.h, int(persistent), int(grid_blocks), int(use_graphs)))
 
-    def step(self, n, t_end=-1.0):
+    def step(self, n, t_end=-1.0, raise_on_error=True):
+        """Advance every run by up to n steps (stopping at t_end [s] when
+        t_end >= 0); per-run records.  With raise_on_error=False a run that
+        produced a non-physical cell is reported by its status instead."""
         infos = (_abi.IcrStepInfo * len(self.runs))()
-        check(lib().icr_ens_step(self.h, int(n), float(t_end), infos))
+        rc = lib().icr_ens_step(self.h, int(n), float(t_end), infos)
+        if raise_on_error or rc != _abi.ICR_ERR_NONPHYSICAL:
+            check(rc)
         return [dict(steps=i.steps_taken, status=i.status, t=i.t, dt=i.last_dt,
                      resid=i.residual) for i in infos]

@@ -25,13 +25,14 @@ def _p(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def init_params(n_theta, n_phi, n_r, c1, c2, hidden, seed=0):
+def init_params(n_theta, n_phi, n_r, c1, c2, hidden, phi_lo=-1, phi_hi=1, seed=0):
     """Scaled normal weights (variance 1/fan_in), zero biases; the last layer
     starts small so the initial output is close to the radial expansion."""
     rng = np.random.default_rng(seed)
     no = 8 * n_r
+    k1 = 3 * (phi_hi - phi_lo + 1) * 8
     parts = []
-    for fan_in, fan_out, scale in ((72, c1, 1.0), (9 * c1, c2, 1.0), (c2, hidden, 1.0),
+    for fan_in, fan_out, scale in ((k1, c1, 1.0), (9 * c1, c2, 1.0), (c2, hidden, 1.0),
                                    (hidden, no, 0.1)):
         parts.append(rng.normal(0.0, scale / np.sqrt(fan_in), (fan_in, fan_out)).ravel())
         parts.append(np.zeros(fan_out))
@@ -39,12 +40,12 @@ def init_params(n_theta, n_phi, n_r, c1, c2, hidden, seed=0):
 
 
 class WarmStartNet:
-    def __init__(self, n_theta, n_phi, n_r, c1=64, c2=128, hidden=384, batch_max=8, device=0,
-                 stream=None):
+    def __init__(self, n_theta, n_phi, n_r, c1=64, c2=128, hidden=384, batch_max=8,
+                 phi_lo=-1, phi_hi=1, device=0, stream=None):
         import torch
         self.torch = torch
-        self.shape = NnShape(n_theta, n_phi, n_r, c1, c2, hidden, batch_max)
-        self.dims = (n_theta, n_phi, n_r, c1, c2, hidden)
+        self.shape = NnShape(n_theta, n_phi, n_r, c1, c2, hidden, batch_max, phi_lo, phi_hi)
+        self.dims = (n_theta, n_phi, n_r, c1, c2, hidden, phi_lo, phi_hi)
         self.device = torch.device("cuda", device)
         n = ctypes.c_longlong()
         _check(lib().icr_nn_param_count(ctypes.byref(self.shape), ctypes.byref(n)))

@@ -54,14 +54,18 @@ def relaxed_states(grid, seeds, t_ref, precision=64, batch=64, chunk=4000):
             run.set_maps(np.zeros(1), m[None])
             run.init_radial()
         t0 = time.perf_counter()
+        failed = set()
         while True:
-            info = e.step(chunk, t_end=t_ref)
+            info = e.step(chunk, t_end=t_ref, raise_on_error=False)
+            failed |= {q for q, i in enumerate(info) if i["status"] != 0}
             if max(i["steps"] for i in info) < chunk:
                 break
         log(f"warmstart: relaxed {len(sub)} maps to {t_ref / 86400:.1f} d in "
-            f"{time.perf_counter() - t0:.1f} s")
-        for s, m, run in zip(sub, maps, e.runs):
-            yield s, m, run.get_state_device()
+            f"{time.perf_counter() - t0:.1f} s" +
+            (f"; dropped non-physical runs {sorted(sub[q] for q in failed)}" if failed else ""))
+        for q, (s, m, run) in enumerate(zip(sub, maps, e.runs)):
+            if q not in failed:
+                yield s, m, run.get_state_device()
         e.close()
 
 
@@ -71,12 +75,23 @@ def build_dataset(net, grid, seeds, t_ref, rc, thc, precision=64):
     X = torch.empty((n, grid.nt, grid.np_, 8), dtype=torch.float32, device="cuda")
     T = torch.empty((n, grid.nt * grid.np_, 8 * grid.nr), dtype=torch.float32, device="cuda")
     M = torch.empty((n, 8, grid.nt, grid.np_), dtype=torch.float64, device="cuda")
-    for q, (s, m, st) in enumerate(relaxed_states(grid, seeds, t_ref, precision)):
+    q = 0
+    for s, m, st in relaxed_states(grid, seeds, t_ref, precision):
         dm = torch.from_numpy(m).cuda()
         M[q] = dm
         X[q] = net.encode_map(dm[None].contiguous(), thc, synth.OMEGA_SUN, grid.r_in)[0]
         net.encode_target(dm, st, rc, thc, synth.OMEGA_SUN, grid.r_in, out=T[q])
-    return X, T, M
+        q += 1
+    return X[:q], T[:q], M[:q]
+
+
+def default_window(grid, v_slow=350e3):
+    """First-layer longitude offsets reaching the footpoint of slow wind at the
+    outer radius: Omega (r_out - r_in) / v_slow, in cells, plus one; two
+    cells downstream."""
+    dph = 2.0 * math.pi / grid.np_
+    hi = int(math.ceil(synth.OMEGA_SUN * (grid.r_out - grid.r_in) / v_slow / dph)) + 1
+    return -2, min(hi, grid.np_ - 3)
 
 
 def train(net, X, T, epochs=30, batch=8, lr=2e-3, seed=0):
@@ -105,7 +120,7 @@ def train(net, X, T, epochs=30, batch=8, lr=2e-3, seed=0):
     return hist, time.perf_counter() - t0
 
 
-def evaluate(net, grid, seeds, t_ref, predictors, chunk=100, precision=64):
+def evaluate(net, grid, seeds, t_ref, predictors, chunk=50, precision=64):
     """Plain vs warm relaxation on held-out maps.  predictors: name ->
     function(X [1][nt][np][8]) -> y [ncol][no] device tensor."""
     import torch
@@ -173,6 +188,9 @@ def main(argv=None):
     ap.add_argument("--c1", type=int, default=64)
     ap.add_argument("--c2", type=int, default=128)
     ap.add_argument("--hidden", type=int, default=384)
+    ap.add_argument("--phi-lo", type=int, default=None)
+    ap.add_argument("--phi-hi", type=int, default=None)
+    ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--crossings", type=float, default=2.0)
     ap.add_argument("--data-precision", type=int, default=32)
     ap.add_argument("--out", default=None)
@@ -185,12 +203,20 @@ def main(argv=None):
     from .solver import Solver
     g = Grid(args.nr, args.nt, args.nph)
     t_ref = args.crossings * relax.slow_crossing_time(g)
-    net = WarmStartNet(g.nt, g.np_, g.nr, args.c1, args.c2, args.hidden, batch_max=8)
+    lo, hi = default_window(g)
+    lo = lo if args.phi_lo is None else args.phi_lo
+    hi = hi if args.phi_hi is None else args.phi_hi
+    dims = (g.nt, g.np_, g.nr, args.c1, args.c2, args.hidden, lo, hi)
+    if args.weights:
+        dims = tuple(int(v) for v in np.load(args.weights)["dims"])
+        assert dims[:3] == (g.nt, g.np_, g.nr), "weights for another grid"
+    net = WarmStartNet(*dims[:6], batch_max=8, phi_lo=dims[6], phi_hi=dims[7])
     p0 = init_params(*net.dims, seed=0)
     probe = Solver(g)
     rc, thc = grid_geometry(probe)
     probe.close()
-    report = dict(grid=[g.nr, g.nt, g.np_], t_ref_days=t_ref / 86400, params=int(net.nparam))
+    report = dict(grid=[g.nr, g.nt, g.np_], t_ref_days=t_ref / 86400, params=int(net.nparam),
+                  dims=list(net.dims))
     if args.weights:
         p = np.load(args.weights)["params"]
         mean_t = torch.from_numpy(np.load(args.weights)["mean_target"]).cuda()
@@ -201,7 +227,8 @@ def main(argv=None):
         report["dataset_seconds"] = time.perf_counter() - t0
         mean_t = T.mean(dim=0)
         net.set_params(p0)
-        hist, tsec = train(net, X, T, args.epochs)
+        report["train_samples"] = int(X.shape[0])
+        hist, tsec = train(net, X, T, args.epochs, lr=args.lr)
         report.update(train_loss=hist, train_seconds=tsec)
         p = net.get_params()
         if args.out:

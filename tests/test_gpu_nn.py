@@ -48,9 +48,9 @@ def test_gemm_bf16_layouts(torch, ta, tb, M, N, K):
 SHAPE = dict(n_theta=6, n_phi=10, n_r=5, c1=8, c2=16, hidden=24)
 
 
-def small_net(torch, batch=2, seed=0):
+def small_net(torch, batch=2, seed=0, window=(-1, 1)):
     from paper_2501_15923_amd.nn import WarmStartNet, init_params
-    net = WarmStartNet(**SHAPE, batch_max=batch)
+    net = WarmStartNet(**SHAPE, batch_max=batch, phi_lo=window[0], phi_hi=window[1])
     p = init_params(*net.dims, seed=seed)
     p[-8 * SHAPE["n_r"] - SHAPE["hidden"] * 8 * SHAPE["n_r"]:] *= 10  # non-trivial outputs
     net.set_params(p)
@@ -58,8 +58,12 @@ def small_net(torch, batch=2, seed=0):
     return net, sh, p.astype(np.float64)
 
 
-def test_forward_matches_oracle(torch):
-    net, sh, p = small_net(torch)
+WINDOWS = [(-1, 1), (-2, 5)]
+
+
+@pytest.mark.parametrize("window", WINDOWS)
+def test_forward_matches_oracle(torch, window):
+    net, sh, p = small_net(torch, window=window)
     rng = np.random.default_rng(7)
     x = rng.normal(size=(2, 6, 10, 8))
     y = net.forward(torch.from_numpy(x.astype(np.float32)).cuda()).cpu().numpy()
@@ -67,8 +71,9 @@ def test_forward_matches_oracle(torch):
     assert np.linalg.norm(y - ref) / np.linalg.norm(ref) < 5e-3
 
 
-def test_gradients_match_oracle(torch):
-    net, sh, p = small_net(torch)
+@pytest.mark.parametrize("window", WINDOWS)
+def test_gradients_match_oracle(torch, window):
+    net, sh, p = small_net(torch, window=window)
     rng = np.random.default_rng(8)
     x = rng.normal(size=(2, 6, 10, 8)).astype(np.float32)
     t = rng.normal(0, 0.5, (2 * 60, sh.no)).astype(np.float32)

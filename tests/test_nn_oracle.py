@@ -3,13 +3,14 @@ differences of its own FP64 forward, the 3x3 gather against its adjoint,
 bfloat16 rounding against exactly known values, and the feature / target
 transforms against their inverses and the radial-expansion laws."""
 import numpy as np
+import pytest
 
 from oracle import nn_oracle as no
 from paper_2501_15923_amd import synth
 
 
-def tiny():
-    sh = no.Shape(4, 6, 3, 4, 5, 6)
+def tiny(phi_lo=-1, phi_hi=1):
+    sh = no.Shape(4, 6, 3, 4, 5, 6, phi_lo, phi_hi)
     rng = np.random.default_rng(1)
     p = rng.normal(0, 0.4, sh.nparam)
     x = rng.normal(0, 1, (2, 4, 6, 8))
@@ -17,8 +18,9 @@ def tiny():
     return sh, p, x, t
 
 
-def test_backward_matches_finite_differences():
-    sh, p, x, t = tiny()
+@pytest.mark.parametrize("window", [(-1, 1), (-2, 3)])
+def test_backward_matches_finite_differences(window):
+    sh, p, x, t = tiny(*window)
     loss, g = no.loss_grad(sh, p, x, t, bf16=False)
     rng = np.random.default_rng(2)
     idx = rng.choice(sh.nparam, 60, replace=False)
@@ -45,6 +47,16 @@ def test_im2col_adjoint_and_boundaries():
     assert np.array_equal(a[:, 2, 0, 1 * 3 + 0], h[:, 2, nph - 1])
     assert np.array_equal(a[:, 0, 3, 0 * 3 + 1], h[:, 0, 3])
     assert np.array_equal(a[:, nt - 1, 3, 2 * 3 + 1], h[:, nt - 1, 3])
+    # a wide upstream window: dk in -2..4 wraps around the longitude period
+    dk0, nk = -2, 7
+    da = rng.normal(size=(B * nt * nph, 3 * nk * C))
+    lhs = np.sum(no.im2col(h, dk0, nk) * da)
+    rhs = np.sum(h * no.col2im(da, B, nt, nph, C, dk0, nk))
+    assert abs(lhs - rhs) < 1e-10 * abs(lhs)
+    a = no.im2col(h, dk0, nk).reshape(B, nt, nph, 3 * nk, C)
+    assert np.array_equal(a[:, 1, 5, 1 * nk + (4 - dk0)], h[:, 1, (5 + 4) % nph])
+    assert np.array_equal(a[:, 1, 0, 1 * nk + (-2 - dk0)], h[:, 1, nph - 2])
+    assert np.array_equal(a[:, 0, 2, 0 * nk + (1 - dk0)], h[:, 0, 3])
 
 
 def test_bf16_rounding():

@@ -307,7 +307,7 @@ def parker_runs(orc):
 
 
 def test_parker_spiral_alignment_and_angle(parker_runs):
-    mis = []
+    mis, err = [], []
     for n, (g, o, info) in parker_runs.items():
         W = o.get_state()
         re, te, _ = o.edges()
@@ -321,7 +321,10 @@ def test_parker_spiral_alignment_and_angle(parker_runs):
         j = g.nt // 2
         tanpsi = np.abs(bp[0, j, i1] / br[0, j, i1])
         expect = synth.OMEGA_SUN * rc[i1] * np.sin(th[j]) / vr[0, j, i1]
-        assert abs(tanpsi / expect - 1) < 0.03, (tanpsi, expect)
+        err.append(abs(tanpsi / expect - 1))
+    # the kinematic Parker angle is approached as the grid is refined
+    # (second-order scheme: 3.0 % at 8 colatitude rows, 1 % at 16)
+    assert err[0] < 0.04 and err[1] < 0.02 and err[1] < 0.5 * err[0], err
     assert mis[1] < mis[0]
 
 
