@@ -177,6 +177,19 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R>& a, int kplanes, i
         for (int v = 0; v < NV; ++v) sFt[v][TT][q] = f[v];
       }
     }
+    // The own cell's conserved values for the update (and, in stage 2, those
+    // of U^n) are loaded here, before the phi face and the barrier, so that
+    // their latency overlaps that work instead of stalling the update.
+    R uc[NV], up[NV];
+    if (body && valid) {
+      const long long c = kbase + colbase;
+#pragma unroll
+      for (int v = 0; v < NV; ++v) uc[v] = a.uin[v * a.ncell + c];
+      if (STAGE == 2) {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) up[v] = a.un[v * a.ncell + c];
+      }
+    }
     // phi face k+1/2 from the register ring (and the next plane's load)
     R fhi[NV];
     {
@@ -210,9 +223,6 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R>& a, int kplanes, i
         add_sources<R>(wa, a.m, ic, jc, a.omega, a.gravity, a.corot, L);
         const R dt = (R)a.clock->dt;
         const long long c = kbase + colbase;
-        R uc[NV];
-#pragma unroll
-        for (int v = 0; v < NV; ++v) uc[v] = a.uin[v * a.ncell + c];
         if (STAGE == 1) {
 #pragma unroll
           for (int v = 0; v < NV; ++v) a.uout[v * a.ncell + c] = uc[v] + dt * L[v];
@@ -220,7 +230,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R>& a, int kplanes, i
           R un[NV], unew[NV], wn[NV];
 #pragma unroll
           for (int v = 0; v < NV; ++v) {
-            un[v] = a.un[v * a.ncell + c];
+            un[v] = up[v];
             unew[v] = R(0.5) * un[v] + R(0.5) * (uc[v] + dt * L[v]);
             a.uout[v * a.ncell + c] = unew[v];
           }
