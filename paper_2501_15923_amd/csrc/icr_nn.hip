@@ -81,17 +81,22 @@ __global__ void __launch_bounds__(256) k_gemm(const uint16_t* __restrict__ A,
                                               const uint16_t* __restrict__ B,
                                               float* __restrict__ C,
                                               const float* __restrict__ bias, int M, int N,
-                                              int K, int lda, int ldb, int ldc) {
+                                              int Kfull, int lda, int ldb, int ldc, int kchunk) {
   __shared__ __attribute__((aligned(16))) uint16_t sA[BM][KP];
   __shared__ __attribute__((aligned(16))) uint16_t sB[BN][KP];
   const int m0 = blockIdx.y * BM, n0 = blockIdx.x * BN;
+  // split K: block z covers k in [z kchunk, min(K, (z + 1) kchunk)) and writes
+  // its partial product to slab z of C (slabs M x ldc apart)
+  const int kbeg = blockIdx.z * kchunk;
+  const int K = Kfull < kbeg + kchunk ? Kfull : kbeg + kchunk;
+  C += (long long)blockIdx.z * M * ldc;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int wm = (w >> 1) * 64, wn = (w & 1) * 64;
   f32x16 acc[2][2];
   for (int a = 0; a < 2; ++a)
     for (int b = 0; b < 2; ++b)
       for (int q = 0; q < 16; ++q) acc[a][b][q] = 0.f;
-  for (int k0 = 0; k0 < K; k0 += BK) {
+  for (int k0 = kbeg; k0 < K; k0 += BK) {
     __syncthreads();
     load_tile<TA>(A, lda, m0, k0, M, K, sA);
     load_tile<TB ? 0 : 1>(B, ldb, n0, k0, N, K, sB);
@@ -123,17 +128,66 @@ __global__ void __launch_bounds__(256) k_gemm(const uint16_t* __restrict__ A,
     }
 }
 
+void gemm_launch(int ta, int tb, const uint16_t* A, const uint16_t* B, float* C,
+                 const float* bias, int M, int N, int K, int lda, int ldb, int ldc, int splits,
+                 int kchunk, hipStream_t s) {
+  const dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM, splits), blk(256);
+  if (!ta && !tb)
+    hipLaunchKernelGGL((k_gemm<0, 0>), grid, blk, 0, s, A, B, C, bias, M, N, K, lda, ldb, ldc,
+                       kchunk);
+  else if (!ta && tb)
+    hipLaunchKernelGGL((k_gemm<0, 1>), grid, blk, 0, s, A, B, C, bias, M, N, K, lda, ldb, ldc,
+                       kchunk);
+  else if (ta && !tb)
+    hipLaunchKernelGGL((k_gemm<1, 0>), grid, blk, 0, s, A, B, C, bias, M, N, K, lda, ldb, ldc,
+                       kchunk);
+  else
+    hipLaunchKernelGGL((k_gemm<1, 1>), grid, blk, 0, s, A, B, C, bias, M, N, K, lda, ldb, ldc,
+                       kchunk);
+}
+
 void gemm(int ta, int tb, const uint16_t* A, const uint16_t* B, float* C, const float* bias, int M,
           int N, int K, int lda, int ldb, int ldc, hipStream_t s) {
-  const dim3 grid((N + BN - 1) / BN, (M + BM - 1) / BM), blk(256);
-  if (!ta && !tb)
-    hipLaunchKernelGGL((k_gemm<0, 0>), grid, blk, 0, s, A, B, C, bias, M, N, K, lda, ldb, ldc);
-  else if (!ta && tb)
-    hipLaunchKernelGGL((k_gemm<0, 1>), grid, blk, 0, s, A, B, C, bias, M, N, K, lda, ldb, ldc);
-  else if (ta && !tb)
-    hipLaunchKernelGGL((k_gemm<1, 0>), grid, blk, 0, s, A, B, C, bias, M, N, K, lda, ldb, ldc);
-  else
-    hipLaunchKernelGGL((k_gemm<1, 1>), grid, blk, 0, s, A, B, C, bias, M, N, K, lda, ldb, ldc);
+  gemm_launch(ta, tb, A, B, C, bias, M, N, K, lda, ldb, ldc, 1, (K + BK - 1) / BK * BK, s);
+}
+
+// Split of the reduction dimension for products whose output has few tiles
+// and whose K is long (the weight gradients, K = rows of the batch): enough
+// (tile, slab) blocks to fill the chip, each slab a multiple of BK.
+struct Split {
+  int slabs, kchunk;
+};
+Split ksplit(int M, int N, int K) {
+  const int tiles = ((M + BM - 1) / BM) * ((N + BN - 1) / BN);
+  int want = (1024 + tiles - 1) / tiles;
+  const int most = (K + 8 * BK - 1) / (8 * BK);  // at least 8 k-steps per slab
+  want = want < 1 ? 1 : (want > most ? most : want);
+  const int kchunk = ((K + want - 1) / want + BK - 1) / BK * BK;
+  return Split{(K + kchunk - 1) / kchunk, kchunk};
+}
+
+// C[i] = sum over slabs z (in order) of P[z][i]
+__global__ void k_sum_slabs(const float* __restrict__ part, int slabs, long long n,
+                            float* __restrict__ C) {
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float acc = 0.f;
+  for (int z = 0; z < slabs; ++z) acc += part[(long long)z * n + i];
+  C[i] = acc;
+}
+
+// weight gradient C [M][N] (contiguous) from a product over a long K
+void gemm_wgrad(int ta, int tb, const uint16_t* A, const uint16_t* B, float* C, int M, int N,
+                int K, int lda, int ldb, float* scratch, hipStream_t s) {
+  const Split sp = ksplit(M, N, K);
+  if (sp.slabs == 1) {
+    gemm(ta, tb, A, B, C, nullptr, M, N, K, lda, ldb, N, s);
+    return;
+  }
+  gemm_launch(ta, tb, A, B, scratch, nullptr, M, N, K, lda, ldb, N, sp.slabs, sp.kchunk, s);
+  const long long n = (long long)M * N;
+  hipLaunchKernelGGL(k_sum_slabs, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, scratch,
+                     sp.slabs, n, C);
 }
 
 // ------------------------------------------------------------ elementwise --
@@ -220,13 +274,49 @@ __global__ void k_col2im(const float* __restrict__ da, float* __restrict__ dh, i
   dh[i] = s;
 }
 
-// db[n] = sum_m dZ[m][n] (fixed order)
-__global__ void k_colsum(const float* __restrict__ dz, float* __restrict__ db, int M, int N) {
+// Column sums db[n] = sum_m dZ[m][n] in two passes with a fixed order:
+// block (x, slab) sums rows of its slab for 64 columns (4 row phases per
+// column, combined in order), then one thread per column adds the slabs.
+constexpr int CS_SLABS = 64;
+template <bool DIFF>
+__global__ void __launch_bounds__(256) k_colsum_part(const float* __restrict__ a,
+                                                     const float* __restrict__ b, int M, int N,
+                                                     double* __restrict__ part) {
+  __shared__ double sh[4][64];
+  const int n = blockIdx.x * 64 + (threadIdx.x & 63), ph = threadIdx.x >> 6;
+  const int rows = (M + CS_SLABS - 1) / CS_SLABS;
+  const int m0 = blockIdx.y * rows, m1 = m0 + rows < M ? m0 + rows : M;
+  double acc = 0.0;
+  if (n < N)
+    for (int m = m0 + ph; m < m1; m += 4) {
+      const long long i = (long long)m * N + n;
+      acc += DIFF ? (double)(a[i] - b[i]) : (double)a[i];
+    }
+  sh[ph][threadIdx.x & 63] = acc;
+  __syncthreads();
+  if (ph == 0 && n < N)
+    part[(long long)blockIdx.y * N + n] = ((sh[0][threadIdx.x] + sh[1][threadIdx.x]) +
+                                           sh[2][threadIdx.x]) + sh[3][threadIdx.x];
+}
+
+__global__ void k_colsum_fin(const double* __restrict__ part, int N, double scale,
+                             float* __restrict__ db) {
   const int n = blockIdx.x * blockDim.x + threadIdx.x;
   if (n >= N) return;
-  double s = 0.0;
-  for (int m = 0; m < M; ++m) s += dz[(long long)m * N + n];
-  db[n] = (float)s;
+  double acc = 0.0;
+  for (int z = 0; z < CS_SLABS; ++z) acc += part[(long long)z * N + n];
+  db[n] = (float)(acc * scale);
+}
+
+// db = scale * column sums of A (or of A - B when b != nullptr)
+void colsum(const float* a, const float* b, int M, int N, double scale, float* db,
+            double* scratch, hipStream_t s) {
+  const dim3 grid((N + 63) / 64, CS_SLABS);
+  if (b)
+    hipLaunchKernelGGL(k_colsum_part<true>, grid, dim3(256), 0, s, a, b, M, N, scratch);
+  else
+    hipLaunchKernelGGL(k_colsum_part<false>, grid, dim3(256), 0, s, a, b, M, N, scratch);
+  hipLaunchKernelGGL(k_colsum_fin, dim3((N + 255) / 256), dim3(256), 0, s, scratch, N, scale, db);
 }
 
 // dY = 2 (Y - T) / count (BF16 for the products), loss partial sums per block
@@ -250,12 +340,20 @@ __global__ void k_mse(const float* __restrict__ y, const float* __restrict__ t,
   if (threadIdx.x == 0) part[blockIdx.x] = sh[0];
 }
 
-__global__ void k_sum(const double* __restrict__ part, int n, double* __restrict__ out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double s = 0.0;
-    for (int i = 0; i < n; ++i) s += part[i];
-    out[0] = s;
+// out = sum of part[0..n): one block of 256, strided partial sums, then a
+// fixed tree
+__global__ void __launch_bounds__(256) k_sum(const double* __restrict__ part, int n,
+                                             double* __restrict__ out) {
+  __shared__ double sh[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) acc += part[i];
+  sh[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sh[threadIdx.x] += sh[threadIdx.x + o];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) out[0] = sh[0];
 }
 
 // Adam on FP32 masters, BF16 copies refreshed
@@ -450,6 +548,8 @@ struct icr_nn {
   uint16_t *dyb, *dz3b, *dz2b, *dz1b;
   float *dh3, *dz3, *dh2, *dz2, *da2, *dh1, *dz1;
   double *part, *loss;
+  float* split;    // split-K partial products of the weight gradients
+  double* cpart;   // column-sum partials [CS_SLABS][widest layer]
   // parameter views
   float *W1, *b1, *W2, *b2, *W3, *b3, *W4, *b4;
   uint16_t *W1b, *W2b, *W3b, *W4b;
@@ -498,13 +598,28 @@ size_t layout(const icr_nn_shape& s, icr_nn* n) {
   const long long nblk = (M * z.no + 255) / 256;
   double* part = (double*)take(8 * nblk);
   double* loss = (double*)take(8);
+  long long nsplit = 1;
+  {
+    const int dims[4][2] = {{z.h, z.no}, {z.c2, z.h}, {z.k2, z.c2}, {z.k1, z.c1}};
+    for (const auto& d : dims) {
+      const Split sp = ksplit(d[0], d[1], (int)M);
+      if (sp.slabs > 1 && (long long)sp.slabs * d[0] * d[1] > nsplit)
+        nsplit = (long long)sp.slabs * d[0] * d[1];
+    }
+  }
+  float* split = (float*)take(4 * nsplit);
+  int wmax = z.no > z.h ? z.no : z.h;
+  wmax = wmax > z.c2 ? wmax : z.c2;
+  wmax = wmax > z.c1 ? wmax : z.c1;
+  double* cpart = (double*)take(8LL * CS_SLABS * wmax);
   if (n) {
     n->z = z;
     n->p = p; n->g = g; n->m = m; n->v = v; n->pb = pb;
     n->x = x; n->xb = xb; n->a1 = a1; n->z1 = z1; n->h1 = h1; n->a2 = a2; n->z2 = z2;
     n->h2 = h2; n->z3 = z3; n->h3 = h3; n->y = y; n->dyb = dyb; n->dh3 = dh3; n->dz3 = dz3;
     n->dz3b = dz3b; n->dh2 = dh2; n->dz2 = dz2; n->dz2b = dz2b; n->da2 = da2; n->dh1 = dh1;
-    n->dz1 = dz1; n->dz1b = dz1b; n->part = part; n->loss = loss;
+    n->dz1 = dz1; n->dz1b = dz1b; n->part = part; n->loss = loss; n->split = split;
+    n->cpart = cpart;
     long long o = 0;
     auto view = [&](long long cnt, float*& fp, float*& gp, uint16_t** bp) {
       fp = p + o;
@@ -554,42 +669,31 @@ void backward(icr_nn* n, int B, const float* t_dev) {
   const int nblk = (int)((ny + 255) / 256);
   hipLaunchKernelGGL(k_mse, dim3(nblk), dim3(256), 0, s, n->y, t_dev, n->dyb, n->part, ny,
                      1.f / (float)ny);
-  hipLaunchKernelGGL(k_sum, dim3(1), dim3(64), 0, s, n->part, nblk, n->loss);
+  hipLaunchKernelGGL(k_sum, dim3(1), dim3(256), 0, s, n->part, nblk, n->loss);
   // decoder layer 2: Y = H3 W4 + b4
-  gemm(1, 0, n->h3, n->dyb, n->gW4, nullptr, z.h, z.no, (int)M, z.h, z.no, z.no, s);
+  gemm_wgrad(1, 0, n->h3, n->dyb, n->gW4, z.h, z.no, (int)M, z.h, z.no, n->split, s);
   // db4 = colsum(dY) needs dY in FP32: recompute as 2(Y - T)/ny inside a colsum of Y - T
   gemm(0, 1, n->dyb, n->W4b, n->dh3, nullptr, (int)M, z.h, z.no, z.no, z.no, z.h, s);
   hipLaunchKernelGGL(k_silu_back, g1(M * z.h), dim3(256), 0, s, n->dh3, n->z3, n->dz3, n->dz3b,
                      M * z.h);
-  gemm(1, 0, n->h2, n->dz3b, n->gW3, nullptr, z.c2, z.h, (int)M, z.c2, z.h, z.h, s);
-  hipLaunchKernelGGL(k_colsum, g1(z.h), dim3(256), 0, s, n->dz3, n->gb3, (int)M, z.h);
+  gemm_wgrad(1, 0, n->h2, n->dz3b, n->gW3, z.c2, z.h, (int)M, z.c2, z.h, n->split, s);
+  colsum(n->dz3, nullptr, (int)M, z.h, 1.0, n->gb3, n->cpart, s);
   gemm(0, 1, n->dz3b, n->W3b, n->dh2, nullptr, (int)M, z.c2, z.h, z.h, z.h, z.c2, s);
   hipLaunchKernelGGL(k_silu_back, g1(M * z.c2), dim3(256), 0, s, n->dh2, n->z2, n->dz2, n->dz2b,
                      M * z.c2);
-  gemm(1, 0, n->a2, n->dz2b, n->gW2, nullptr, z.k2, z.c2, (int)M, z.k2, z.c2, z.c2, s);
-  hipLaunchKernelGGL(k_colsum, g1(z.c2), dim3(256), 0, s, n->dz2, n->gb2, (int)M, z.c2);
+  gemm_wgrad(1, 0, n->a2, n->dz2b, n->gW2, z.k2, z.c2, (int)M, z.k2, z.c2, n->split, s);
+  colsum(n->dz2, nullptr, (int)M, z.c2, 1.0, n->gb2, n->cpart, s);
   gemm(0, 1, n->dz2b, n->W2b, n->da2, nullptr, (int)M, z.k2, z.c2, z.c2, z.c2, z.k2, s);
   hipLaunchKernelGGL(k_col2im, g1(M * z.c1), dim3(256), 0, s, n->da2, n->dh1, B, nt, np, z.c1,
                      -1, 3);
   hipLaunchKernelGGL(k_silu_back, g1(M * z.c1), dim3(256), 0, s, n->dh1, n->z1, n->dz1, n->dz1b,
                      M * z.c1);
-  gemm(1, 0, n->a1, n->dz1b, n->gW1, nullptr, z.k1, z.c1, (int)M, z.k1, z.c1, z.c1, s);
-  hipLaunchKernelGGL(k_colsum, g1(z.c1), dim3(256), 0, s, n->dz1, n->gb1, (int)M, z.c1);
+  gemm_wgrad(1, 0, n->a1, n->dz1b, n->gW1, z.k1, z.c1, (int)M, z.k1, z.c1, n->split, s);
+  colsum(n->dz1, nullptr, (int)M, z.c1, 1.0, n->gb1, n->cpart, s);
 }
 
 }  // namespace
 
-// db4 = sum over rows of dY, with dY = 2 (Y - T)/ny in FP32
-namespace icrnn {
-__global__ void k_colsum_dy(const float* __restrict__ y, const float* __restrict__ t,
-                            float* __restrict__ db, int M, int N, float scale) {
-  const int n = blockIdx.x * blockDim.x + threadIdx.x;
-  if (n >= N) return;
-  double s = 0.0;
-  for (int m = 0; m < M; ++m) s += (double)(y[(long long)m * N + n] - t[(long long)m * N + n]);
-  db[n] = (float)(2.0 * s * scale);
-}
-}  // namespace icrnn
 
 extern "C" {
 
@@ -669,8 +773,7 @@ int icr_nn_loss_grad(icr_nn* n, int batch, const float* x_dev, const float* t_de
   backward(n, batch, t_dev);
   const long long M = (long long)batch * n->z.ncol;
   const long long ny = M * n->z.no;
-  hipLaunchKernelGGL(k_colsum_dy, g1(n->z.no), dim3(256), 0, n->stream, n->y, t_dev, n->gb4,
-                     (int)M, n->z.no, 1.f / (float)ny);
+  colsum(n->y, t_dev, (int)M, n->z.no, 2.0 / (double)ny, n->gb4, n->cpart, n->stream);
   NN_TRY(hipGetLastError());
   double l = 0.0;
   NN_TRY(hipMemcpyAsync(&l, n->loss, 8, hipMemcpyDeviceToHost, n->stream));
