@@ -54,6 +54,8 @@ def parse():
                          "uneven runs in one persistent launch vs 64 sequential runs")
     ap.add_argument("--runs", type=int, default=64)
     ap.add_argument("--maps", type=int, default=4, help="held-out maps for --workload relax")
+    ap.add_argument("--ens-grid", default=None,
+                    help="NRxNTxNP: give every ensemble run this grid (default: uneven grids)")
     ap.add_argument("--weights", default=WEIGHTS)
     return ap.parse_args()
 
@@ -68,7 +70,11 @@ def ensemble_bench(args):
     from paper_2501_15923_amd.ensemble import Ensemble
     from paper_2501_15923_amd.solver import Solver
 
-    members = synth.ensemble_members(args.runs)
+    fixed = None
+    if args.ens_grid:
+        nr, nt, nph = (int(v) for v in args.ens_grid.lower().split("x"))
+        fixed = synth.Grid(nr, nt, nph)
+    members = synth.ensemble_members(args.runs, grid=fixed)
     grids = [m["grid"] for m in members]
     cells = sum(g.cells for g in grids)
     log(f"bench: ensemble of {len(grids)} runs, {cells / 1e6:.1f} M cells, fp{args.precision}")
@@ -119,7 +125,8 @@ def ensemble_bench(args):
         "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
         "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": f"f{args.precision}", "data": "synthetic",
-        "config": {"workload": f"ensemble_{len(grids)}_uneven_runs", "cells": cells,
+        "config": {"workload": (f"ensemble_{len(grids)}_runs_{args.ens_grid}" if fixed else
+                                f"ensemble_{len(grids)}_uneven_runs"), "cells": cells,
                    "persistent": int(persistent), "planes": sorted(set(planes))},
         "sequential": {"value": seq, "unit": "cell-updates/s",
                        "ms_per_step": seq_ms / args.steps},

@@ -202,10 +202,11 @@ def cone_cme(seed: int, earth_table: np.ndarray, t_start: float = 12 * HOUR,
     return np.array([t_start, duration, lat, lon, half_width, speed, rho, temp])
 
 
-def ensemble_members(n_runs: int = 64, seed0: int = 100):
+def ensemble_members(n_runs: int = 64, seed0: int = 100, grid: Grid | None = None):
     """Uneven ensemble: per run a grid with n_r ~ U{150..600},
-    n_theta ~ U{30..60}, n_phi ~ U{60..120}, a 10-map sequence and one cone
-    CME with speed U[500, 2000] km/s and half-width U[15, 45] deg."""
+    n_theta ~ U{30..60}, n_phi ~ U{60..120} (or the given grid for every
+    run), a 10-map sequence and one cone CME with speed U[500, 2000] km/s
+    and half-width U[15, 45] deg."""
     runs = []
     for q in range(n_runs):
         seed = seed0 + q
@@ -215,7 +216,7 @@ def ensemble_members(n_runs: int = 64, seed0: int = 100):
         nph = int(rng.integers(60, 121))
         speed = rng.uniform(500e3, 2000e3)
         hw = rng.uniform(15 * DEG, 45 * DEG)
-        g = Grid(nr, nt, nph)
+        g = Grid(nr, nt, nph) if grid is None else grid
         times, maps = dynamic_maps(g, seed)
         earth = orbit_table(3 * DAY, 600.0, AU, 0.0, rng.uniform(0, 2 * math.pi))
         cme = cone_cme(seed, earth, speed=speed, half_width=hw)
