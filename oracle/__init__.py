@@ -73,6 +73,11 @@ def lib():
         L.orc_volumes.argtypes = [P, D]
         L.orc_sample.argtypes = [P, ctypes.c_int, ctypes.c_int, D, D]
         L.orc_divb.argtypes = [P, D]
+        L.orc_set_tracer.argtypes = [P, D]
+        L.orc_get_tracer.argtypes = [P, D]
+        L.orc_tracer_flux.restype = ctypes.c_double
+        L.orc_tracer_flux.argtypes = [P]
+        L.orc_divv.argtypes = [P, D]
         _lib = L
     return _lib
 
@@ -95,12 +100,12 @@ class Oracle:
                  th_min=None, th_max=None, gamma=1.5, omega=2.87e-6, cfl=0.4,
                  flux=FLUX_TVDLF, limiter=LIM_MINMOD, gravity=True, corot=True,
                  bc_transverse=BCT_MAP, bc_mode=BCM_DRIVEN,
-                 slab_bcx=SLABX_OUTFLOW, box=(0, 1, 0, 1, 0, 1)):
+                 slab_bcx=SLABX_OUTFLOW, box=(0, 1, 0, 1, 0, 1), tracer=False):
         from paper_2501_15923_amd import synth
         self.nr, self.nt, self.np_ = nr, nt, nph
         self.geom = geom
         ip = np.array([nr, nt, nph, geom, flux, limiter, int(gravity),
-                       int(corot), bc_transverse, bc_mode, slab_bcx],
+                       int(corot), bc_transverse, bc_mode, slab_bcx, int(tracer)],
                       dtype=np.int32)
         dp = np.array([
             synth.AU * 0.1 if r_in is None else r_in,
@@ -210,4 +215,24 @@ class Oracle:
     def divb(self):
         out = np.zeros((self.np_, self.nt, self.nr))
         lib().orc_divb(self.h, _d(out))
+        return out
+
+    def set_tracer(self, tau):
+        tau = np.ascontiguousarray(np.broadcast_to(tau, (self.np_, self.nt, self.nr)),
+                                   dtype=np.float64)
+        if lib().orc_set_tracer(self.h, _d(tau)) != 0:
+            raise ValueError("oracle built without the tracer")
+
+    def get_tracer(self):
+        out = np.zeros((self.np_, self.nt, self.nr))
+        if lib().orc_get_tracer(self.h, _d(out)) != 0:
+            raise ValueError("oracle built without the tracer")
+        return out
+
+    def tracer_flux(self):
+        return lib().orc_tracer_flux(self.h)
+
+    def divv(self):
+        out = np.zeros((self.np_, self.nt, self.nr))
+        lib().orc_divv(self.h, _d(out))
         return out

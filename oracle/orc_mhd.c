@@ -84,6 +84,12 @@ typedef struct {
   double *volr, *hr, *garea, *ct, *se, *st, *snc, *csc;
   /* scratch */
   double *W, *F, *L, *U0, *U1;
+  /* passive CME tracer (optional): conserved rho*tau with ghosts, its stage
+   * copies and right-hand side, the upwind tau of every padded cell, and the
+   * tracer's boundary-face integral of the last step */
+  int tracer;
+  double *T, *T0, *T1, *LT, *P, *FT;
+  double tbflux;
 } orc_ctx;
 
 static size_t pad_cells(const orc_ctx *c) {
@@ -290,6 +296,7 @@ void *orc_create(const int *ip, const double *dp) {
   c->bc_transverse = ip[8];
   c->bc_mode = ip[9];
   c->slab_bcx = ip[10];
+  c->tracer = ip[11] && ip[3] == GEOM_SPH;
   c->gr = c->nr + 2 * NG;
   c->gt = c->nt + 2 * NG;
   c->gp = c->np + 2 * NG;
@@ -312,6 +319,16 @@ void *orc_create(const int *ip, const double *dp) {
   c->F = xcalloc(n, sizeof(double));
   c->L = xcalloc(n, sizeof(double));
   if (!c->U || !c->U0 || !c->U1 || !c->W || !c->F || !c->L) return 0;
+  if (c->tracer) {
+    size_t m = pad_cells(c);
+    c->T = xcalloc(m, sizeof(double));
+    c->T0 = xcalloc(m, sizeof(double));
+    c->T1 = xcalloc(m, sizeof(double));
+    c->LT = xcalloc(m, sizeof(double));
+    c->P = xcalloc(m, sizeof(double));
+    c->FT = xcalloc(m, sizeof(double));
+    if (!c->T || !c->T0 || !c->T1 || !c->LT || !c->P || !c->FT) return 0;
+  }
   return c;
 }
 
@@ -322,6 +339,7 @@ void orc_destroy(void *h) {
   free(c->rc); free(c->tc); free(c->pc);
   free(c->U); free(c->U0); free(c->U1);
   free(c->W); free(c->F); free(c->L);
+  free(c->T); free(c->T0); free(c->T1); free(c->LT); free(c->P); free(c->FT);
   free(c->tau); free(c->maps); free(c->cme);
   free(c->volr); free(c->hr); free(c->garea); free(c->ct);
   free(c->st); free(c->snc); free(c->csc); free(c->se);
@@ -436,15 +454,22 @@ static void map_at(const orc_ctx *c, double t, int j, int k, double *w) {
  * the time-interpolated map, then the cone-CME overwrite of points whose
  * great-circle distance to the cone axis is within the half-width while the
  * CME is being inserted (Sect. 3.2).  The CME is not magnetised: B is kept. */
+/* 1 when boundary point (j, k) lies inside a cone CME being inserted at t */
+static int in_cme(const orc_ctx *c, double t, int j, int k, int q) {
+  const double *m = c->cme + 8 * q;
+  if (!(t >= m[0] && t < m[0] + m[1])) return 0;
+  double th = c->tc[j], ph = c->pc[k];
+  double cosd = cos(th) * cos(m[2]) + sin(th) * sin(m[2]) * cos(ph - m[3]);
+  return cosd >= cos(m[4]);
+}
+
 static void inner_boundary_prim(const orc_ctx *c, double t, int j, int k,
                                 double *w) {
   map_at(c, t, j, k, w);
-  double th = c->tc[j], ph = c->pc[k];
+  double th = c->tc[j];
   for (int q = 0; q < c->n_cme; ++q) {
     const double *m = c->cme + 8 * q;
-    if (!(t >= m[0] && t < m[0] + m[1])) continue;
-    double cosd = cos(th) * cos(m[2]) + sin(th) * sin(m[2]) * cos(ph - m[3]);
-    if (cosd >= cos(m[4])) {
+    if (in_cme(c, t, j, k, q)) {
       w[0] = m[6];
       w[1] = m[5];
       w[2] = 0.0;
@@ -541,11 +566,53 @@ static void fill_ghosts(orc_ctx *c, double *U, double t) {
  * (r+^2 - r-^2)/2 dtheta. */
 
 /* ---- one evaluation of dU/dt = L(U) over active cells --------------------- */
-static void compute_rhs(orc_ctx *c, double *U, double *L, double *bnd) {
+/* Upwind tracer values tau = (rho tau) / rho of every active cell, and of the
+ * ghost cells: inside an inserted CME cone 1, elsewhere 0 at the inner
+ * boundary; the edge cell's value beyond r_out and the colatitude edges;
+ * periodic in phi. */
+static void tracer_upwind(orc_ctx *c, const double *U, const double *T, double t) {
+  int nr = c->nr, nt = c->nt, np = c->np;
+  for (int k = 0; k < np; ++k)
+    for (int j = 0; j < nt; ++j)
+      for (int i = 0; i < nr; ++i)
+        c->P[IX(c, 0, i, j, k)] = T[IX(c, 0, i, j, k)] / U[IX(c, 0, i, j, k)];
+  for (int k = 0; k < np; ++k)
+    for (int j = 0; j < nt; ++j) {
+      double ind = 0.0;
+      for (int q = 0; q < c->n_cme; ++q)
+        if (in_cme(c, t, j, k, q)) ind = 1.0;
+      for (int g = 1; g <= NG; ++g) {
+        c->P[IX(c, 0, -g, j, k)] = ind;
+        c->P[IX(c, 0, nr - 1 + g, j, k)] = c->P[IX(c, 0, nr - 1, j, k)];
+      }
+    }
+  for (int k = 0; k < np; ++k)
+    for (int i = 0; i < nr; ++i)
+      for (int g = 1; g <= NG; ++g) {
+        c->P[IX(c, 0, i, -g, k)] = c->P[IX(c, 0, i, 0, k)];
+        c->P[IX(c, 0, i, nt - 1 + g, k)] = c->P[IX(c, 0, i, nt - 1, k)];
+      }
+  for (int j = 0; j < nt; ++j)
+    for (int i = 0; i < nr; ++i)
+      for (int g = 1; g <= NG; ++g) {
+        c->P[IX(c, 0, i, j, -g)] = c->P[IX(c, 0, i, j, np - g)];
+        c->P[IX(c, 0, i, j, np - 1 + g)] = c->P[IX(c, 0, i, j, g - 1)];
+      }
+}
+
+/* Right-hand side L = -div F + S of every active cell (and, with the tracer
+ * on, LT = -div(F_rho tau_upwind) from the same mass fluxes). */
+static void compute_rhs(orc_ctx *c, double *U, double *L, double *bnd,
+                        const double *T, double *LT, double *tbnd, double t) {
   int nr = c->nr, nt = c->nt, np = c->np;
   double gam = c->gamma;
   size_t np_cells = pad_cells(c);
   double *W = c->W, *F = c->F;
+  if (T) {
+    tracer_upwind(c, U, T, t);
+    for (size_t o = 0; o < np_cells; ++o) LT[o] = 0.0;
+    *tbnd = 0.0;
+  }
   /* primitives of every padded cell whose ghosts were filled */
 #pragma omp parallel for
   for (long q = 0; q < (long)np_cells; ++q) {
@@ -589,6 +656,18 @@ static void compute_rhs(orc_ctx *c, double *U, double *L, double *bnd) {
           for (int v = 0; v < NV; ++v) F[IX(c, v, i, j, k)] = fs[v];
         }
     (void)n;
+    /* tracer face flux: mass flux times tau of the upwind cell */
+    if (T) {
+#pragma omp parallel for
+      for (int k = 0; k < ek; ++k)
+        for (int j = 0; j < ej; ++j)
+          for (int i = 0; i < ei; ++i) {
+            double fm = F[IX(c, 0, i, j, k)];
+            double up = fm >= 0.0 ? c->P[IX(c, 0, i - di, j - dj, k - dk)]
+                                  : c->P[IX(c, 0, i, j, k)];
+            c->FT[IX(c, 0, i, j, k)] = fm * up;
+          }
+    }
     /* divergence of the face fluxes, face m-1/2 stored at index m */
 #pragma omp parallel for
     for (int k = 0; k < np; ++k)
@@ -611,6 +690,20 @@ static void compute_rhs(orc_ctx *c, double *U, double *L, double *bnd) {
               div = c->hr[i] * dth / (c->ct[j] * dph) * (fp - fm);
             }
             L[IX(c, v, i, j, k)] -= div;
+          }
+          if (T) {
+            double fm = c->FT[IX(c, 0, i, j, k)];
+            double fp = c->FT[IX(c, 0, i + di, j + dj, k + dk)];
+            double div;
+            if (dir == 0) {
+              double rm = c->re[i], rp = c->re[i + 1];
+              div = (rp * rp * fp - rm * rm * fm) / c->volr[i];
+            } else if (dir == 1) {
+              div = c->hr[i] * (c->se[j + 1] * fp - c->se[j] * fm) / c->ct[j];
+            } else {
+              div = c->hr[i] * dth / (c->ct[j] * dph) * (fp - fm);
+            }
+            LT[IX(c, 0, i, j, k)] -= div;
           }
         }
     /* boundary-face integrals (area * flux) of this sweep, for the
@@ -642,6 +735,26 @@ static void compute_rhs(orc_ctx *c, double *U, double *L, double *bnd) {
             }
         bnd[v] += s;
       }
+    if (!periodic && T && c->geom == GEOM_SPH) {
+      double s = 0.0;
+      for (int k = 0; k < np; ++k)
+        for (int j = 0; j < (dir == 1 ? 1 : nt); ++j)
+          for (int i = 0; i < (dir == 0 ? 1 : nr); ++i) {
+            int ih = i + di * nr, jh = j + dj * nt;
+            double am, ap;
+            if (dir == 0) {
+              double r0 = c->re[0], r1 = c->re[nr];
+              am = r0 * r0 * c->ct[j] * dph;
+              ap = r1 * r1 * c->ct[j] * dph;
+            } else {
+              double rm = c->re[i], rp = c->re[i + 1];
+              am = c->se[0] * 0.5 * (rp * rp - rm * rm) * dph;
+              ap = c->se[nt] * 0.5 * (rp * rp - rm * rm) * dph;
+            }
+            s += ap * c->FT[IX(c, 0, ih, jh, k)] - am * c->FT[IX(c, 0, i, j, k)];
+          }
+      *tbnd += s;
+    }
   }
 
   /* source terms at cell centres */
@@ -732,9 +845,21 @@ static long rk2_step(orc_ctx *c, double dt) {
   size_t n = pad_cells(c) * NV;
   int nr = c->nr, nt = c->nt, np = c->np;
   double b1[NV], b2[NV];
+  size_t nt1 = pad_cells(c);
+  double tb1 = 0.0, tb2 = 0.0;
   memcpy(c->U0, c->U, n * sizeof(double));
+  if (c->tracer) memcpy(c->T0, c->T, nt1 * sizeof(double));
   fill_ghosts(c, c->U0, c->t);
-  compute_rhs(c, c->U0, c->L, b1);
+  compute_rhs(c, c->U0, c->L, b1, c->tracer ? c->T0 : 0, c->LT, &tb1, c->t);
+  if (c->tracer) {
+    memcpy(c->T1, c->T0, nt1 * sizeof(double));
+    for (int k = 0; k < np; ++k)
+      for (int j = 0; j < nt; ++j)
+        for (int i = 0; i < nr; ++i) {
+          size_t o = IX(c, 0, i, j, k);
+          c->T1[o] = c->T0[o] + dt * c->LT[o];
+        }
+  }
   memcpy(c->U1, c->U0, n * sizeof(double));
 #pragma omp parallel for
   for (int k = 0; k < np; ++k)
@@ -745,7 +870,16 @@ static long rk2_step(orc_ctx *c, double dt) {
           c->U1[o] = c->U0[o] + dt * c->L[o];
         }
   fill_ghosts(c, c->U1, c->t + dt);
-  compute_rhs(c, c->U1, c->L, b2);
+  compute_rhs(c, c->U1, c->L, b2, c->tracer ? c->T1 : 0, c->LT, &tb2, c->t + dt);
+  if (c->tracer) {
+    for (int k = 0; k < np; ++k)
+      for (int j = 0; j < nt; ++j)
+        for (int i = 0; i < nr; ++i) {
+          size_t o = IX(c, 0, i, j, k);
+          c->T[o] = 0.5 * c->T0[o] + 0.5 * (c->T1[o] + dt * c->LT[o]);
+        }
+    c->tbflux = 0.5 * dt * (tb1 + tb2);
+  }
 #pragma omp parallel for
   for (int k = 0; k < np; ++k)
     for (int j = 0; j < nt; ++j)
@@ -975,7 +1109,71 @@ int orc_init_radial(void *h) {
         for (int v = 0; v < NV; ++v) c->U[IX(c, v, i, j, k)] = u[v];
       }
     }
+  if (c->tracer) memset(c->T, 0, pad_cells(c) * sizeof(double));
   return 0;
+}
+
+/* ---- passive CME tracer ---------------------------------------------------- */
+/* tau [np][nt][nr] (dimensionless, 0 outside CME material) <-> rho tau */
+int orc_set_tracer(void *h, const double *tau) {
+  orc_ctx *c = h;
+  if (!c->tracer) return -1;
+  for (int k = 0; k < c->np; ++k)
+    for (int j = 0; j < c->nt; ++j)
+      for (int i = 0; i < c->nr; ++i)
+        c->T[IX(c, 0, i, j, k)] = c->U[IX(c, 0, i, j, k)] *
+                                  tau[((size_t)k * c->nt + j) * c->nr + i];
+  return 0;
+}
+
+int orc_get_tracer(void *h, double *tau) {
+  orc_ctx *c = h;
+  if (!c->tracer) return -1;
+  for (int k = 0; k < c->np; ++k)
+    for (int j = 0; j < c->nt; ++j)
+      for (int i = 0; i < c->nr; ++i)
+        tau[((size_t)k * c->nt + j) * c->nr + i] =
+            c->T[IX(c, 0, i, j, k)] / c->U[IX(c, 0, i, j, k)];
+  return 0;
+}
+
+/* Boundary-face integral of the tracer flux (rho tau v . n dA, code units)
+ * over the last step: the tracer content changes by minus this amount. */
+double orc_tracer_flux(const void *h) { return ((const orc_ctx *)h)->tbflux; }
+
+/* ---- velocity divergence diagnostic (Fig. 7) ------------------------------ */
+/* Cell-centred finite-volume divergence of v (co-rotating frame) with face
+ * velocities the mean of the two neighbouring cell centres; ghosts filled at
+ * the current time (inner boundary map, zero-gradient outer boundary,
+ * reflecting colatitude edges, periodic phi).  out [np][nt][nr] in 1/s. */
+void orc_divv(void *h, double *out) {
+  orc_ctx *c = h;
+  fill_ghosts(c, c->U, c->t);
+  double dth = c->te[1] - c->te[0], dph = c->pe[1] - c->pe[0];
+  int di[3] = {1, 0, 0}, dj[3] = {0, 1, 0}, dk[3] = {0, 0, 1};
+  for (int k = 0; k < c->np; ++k)
+    for (int j = 0; j < c->nt; ++j)
+      for (int i = 0; i < c->nr; ++i) {
+        double vm[3], vp[3];
+        for (int d = 0; d < 3; ++d) {
+          double u0[NV], um[NV], up[NV], w0[NV], wm[NV], wp[NV];
+          for (int v = 0; v < NV; ++v) {
+            u0[v] = c->U[IX(c, v, i, j, k)];
+            um[v] = c->U[IX(c, v, i - di[d], j - dj[d], k - dk[d])];
+            up[v] = c->U[IX(c, v, i + di[d], j + dj[d], k + dk[d])];
+          }
+          cons_to_prim(c->gamma, u0, w0);
+          cons_to_prim(c->gamma, um, wm);
+          cons_to_prim(c->gamma, up, wp);
+          vm[d] = 0.5 * (wm[1 + d] + w0[1 + d]);
+          vp[d] = 0.5 * (w0[1 + d] + wp[1 + d]);
+        }
+        double rm = c->re[i], rp = c->re[i + 1];
+        double div = (rp * rp * vp[0] - rm * rm * vm[0]) / c->volr[i] +
+                     c->hr[i] * (c->se[j + 1] * vp[1] - c->se[j] * vm[1]) / c->ct[j] +
+                     c->hr[i] * dth / (c->ct[j] * dph) * (vp[2] - vm[2]);
+        out[((size_t)k * c->nt + j) * c->nr + i] = div / u_time();
+      }
 }
 
 /* ---- probes (Sect. 2: sampling at moving locations, stretched grid) ------ */
