@@ -54,6 +54,8 @@ def parse():
                          "uneven runs in one persistent launch vs 64 sequential runs")
     ap.add_argument("--runs", type=int, default=64)
     ap.add_argument("--maps", type=int, default=4, help="held-out maps for --workload relax")
+    ap.add_argument("--tracer", action="store_true",
+                    help="production grid with a cone CME and the passive CME tracer on")
     ap.add_argument("--ens-grid", default=None,
                     help="NRxNTxNP: give every ensemble run this grid (default: uneven grids)")
     ap.add_argument("--weights", default=WEIGHTS)
@@ -233,10 +235,15 @@ def ingest_counters(dirs, precision, out_path):
                  if "copyBuffer" in r["Kernel_Name"])
         return (1 << 31) / v  # bytes per counted unit
 
+    def stage_of(name):
+        # k_stage_lds<R, TR, TT, FLUX, LIM, STAGE, FM>: the sixth template argument
+        if "k_stage_lds<" not in name:
+            return None
+        args = name.split("k_stage_lds<", 1)[1].split(">", 1)[0].split(",")
+        return int(args[5]) if len(args) > 5 else None
+
     def stage2_mean(d):
-        v = [float(r["Counter_Value"]) for r in rows(d)
-             if "k_stage_lds" in r["Kernel_Name"] and r["Kernel_Name"].rstrip(")").split(
-                 "(")[0].endswith(", 2>")]
+        v = [float(r["Counter_Value"]) for r in rows(d) if stage_of(r["Kernel_Name"]) == 2]
         assert v, f"no stage-2 dispatches in {d}"
         return sum(v) / len(v), len(v)
 
@@ -296,13 +303,16 @@ def main():
     from paper_2501_15923_amd import configs
     from paper_2501_15923_amd.solver import Solver
 
-    w = configs.prod_dynamic()
+    w = configs.prod_cme() if args.tracer else configs.prod_dynamic()
     g = w.grid
-    log(f"bench: workload {w.name}, fp{args.precision}, steps {args.steps}, warmup {args.warmup}")
+    log(f"bench: workload {w.name}, fp{args.precision}, steps {args.steps}, warmup {args.warmup}"
+        + (", passive CME tracer on" if args.tracer else ""))
     s = Solver(g, precision=args.precision, probe_log_rows=args.steps + args.warmup + 16,
-               max_traj_pts=w.probes.shape[1])
+               max_traj_pts=w.probes.shape[1], tracer=args.tracer)
     s.set_launch(args.variant, 0, 0, 1)
     s.set_maps(w.times, w.maps)
+    if len(w.cmes):
+        s.set_cmes(w.cmes)
     s.set_probes(w.probes, cadence=600.0)
     s.init_radial()
     s.step(args.warmup)
@@ -349,8 +359,13 @@ def main():
                    "rk": "SSP-RK2", "cfl": w.cfl, "parallelism": "single GPU"},
         "roofline": roof,
     }
+    if args.tracer:
+        # the stage intervals now include the tracer kernels: no stage roofline
+        out["config"]["tracer"] = True
+        out["roofline"] = None
+        out["stage_plus_tracer_ms"] = [round(float(x), 4) for x in kms]
     s.close()
-    if not args.no_cpu:
+    if not args.no_cpu and not args.tracer:
         log(f"bench: CPU oracle baseline, {args.cpu_steps} steps")
         out["cpu_baseline"] = cpu_baseline(w, args.cpu_steps)
     print(json.dumps(out), flush=True)

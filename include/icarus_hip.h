@@ -96,6 +96,8 @@ typedef struct {
   int precision;             /* ICR_PREC_F64 or ICR_PREC_F32             */
   int gravity;               /* 1: include -GM/r^2 e_r                   */
   int corotation;            /* 1: centrifugal + Coriolis sources        */
+  int tracer;                /* 1: carry the passive CME tracer (single
+                                solvers only; ensembles reject it)       */
 } icr_phys;
 
 /* Clock: time [s] since the map time origin, completed RK2 steps, the dt of
@@ -224,6 +226,28 @@ int icr_read_probe_log(icr_solver *s, double *out, int cap, int *n_rec);
  * (clamped to the first / last centre): out [2][n_theta][n_phi] host. */
 int icr_sample_shell(icr_solver *s, double r_m, double *out);
 
+/* Passive CME tracer (the CME density tracer the paper plots and refines on,
+ * Fig. 7 and Sect. 4; solvers created with icr_phys.tracer = 1).  tau is the
+ * mass fraction of CME material, [n_phi][n_theta][n_r] like the state.  The
+ * solver carries rho tau and advects it with each RK stage's own mass
+ * fluxes and the upwind tau.  Material enters through the inner boundary:
+ * tau = 1 where a cone CME is being inserted, 0 elsewhere.  Beyond r_out
+ * and the colatitude edges the edge cell's own tau is used.
+ * icr_init_radial and icr_set_state reset tau to 0.
+ * icr_set_tracer converts tau to rho tau with the current density.
+ * on_device selects device or host memory, as for the state.
+ * ICR_ERR_STATE without the tracer or before a state exists. */
+int icr_set_tracer(icr_solver *s, const double *tau, int on_device);
+int icr_get_tracer(icr_solver *s, double *tau, int on_device);
+
+/* Velocity divergence of the current state [1/s] (the div V diagnostic of the
+ * paper's shock refinement criterion, Fig. 7), [n_phi][n_theta][n_r].
+ * Finite-volume divergence in the co-rotating frame.  The face velocity is
+ * the mean of the two neighbouring cell centres.  The inner ghost is the
+ * boundary primitive at the current time; beyond r_out zero-gradient;
+ * mirror rows (v_theta negated) beyond the colatitude edges; phi periodic. */
+int icr_divv(icr_solver *s, double *out, int on_device);
+
 /* Inner-boundary primitive (SI) the solver would impose at time t_s, after
  * time interpolation and the CME overwrite: out [8][n_theta][n_phi] host. */
 int icr_boundary_at(icr_solver *s, double t_s, double *out);
@@ -232,7 +256,8 @@ int icr_boundary_at(icr_solver *s, double t_s, double *out);
  * (2), 1 = one thread per cell with on-the-fly neighbour primitives, 2 =
  * face-once kernel (LDS tile with halo in r/theta, registers along phi).
  * tile_r: lanes along r per block (variant 1: 64, 128, 256; variant 2: 32,
- * 64; 0 = 64); 256 threads per block.  planes: phi planes per block of
+ * 64; 0 = 64; a solver with the passive tracer keeps 64 for variant 2);
+ * 256 threads per block.  planes: phi planes per block of
  * variant 2 (1..n_phi, 0 = 8).  use_graphs: 1 replays steps from captured
  * HIP graphs.  All tiles and plane counts of one variant give bit-identical
  * results; the two variants agree to rounding. */

@@ -980,6 +980,7 @@ int orc_set_state(void *h, const double *in, int kind) {
           prim_to_cons(c->gamma, a, u);
         for (int v = 0; v < NV; ++v) c->U[IX(c, v, i, j, k)] = u[v];
       }
+  if (c->tracer) memset(c->T, 0, pad_cells(c) * sizeof(double));
   return 0;
 }
 

@@ -27,7 +27,7 @@ class IcrGrid(ctypes.Structure):
 class IcrPhys(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("omega", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("flux", ctypes.c_int), ("limiter", ctypes.c_int), ("precision", ctypes.c_int),
-                ("gravity", ctypes.c_int), ("corotation", ctypes.c_int)]
+                ("gravity", ctypes.c_int), ("corotation", ctypes.c_int), ("tracer", ctypes.c_int)]
 
 
 class IcrClock(ctypes.Structure):
@@ -93,6 +93,9 @@ SIGNATURES = {
     "icr_ens_set_planes": (I, [P, I, I]),
     "icr_ens_set_mode": (I, [P, I, I, I]),
     "icr_ens_step": (I, [P, I, ctypes.c_double, ctypes.POINTER(IcrStepInfo)]),
+    "icr_set_tracer": (I, [P, D, I]),
+    "icr_get_tracer": (I, [P, D, I]),
+    "icr_divv": (I, [P, D, I]),
     "icr_sample_shell": (I, [P, ctypes.c_double, D]),
     # warm-start network (include/icarus_nn.h)
     "icr_nn_last_error": (ctypes.c_char_p, []),

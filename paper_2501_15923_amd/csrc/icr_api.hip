@@ -75,6 +75,7 @@ size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
   size_t u[3], g[2], m64, mr, maps, tau, cme, traj, plog, pout, clock, partials, bout, total;
+  size_t t[3], fm, frout, ftend, tg[2];  // passive tracer (0 when off)
   long long max_blocks;
 };
 
@@ -116,6 +117,13 @@ Layout make_layout(const icr_grid& g, const icr_phys& p) {
   L.clock = take(sizeof(DevClock));
   L.partials = take(sizeof(double) * 4 * (size_t)L.max_blocks);
   L.bout = take(sizeof(double) * NV * plane);
+  if (p.tracer) {
+    for (int q = 0; q < 3; ++q) L.t[q] = take(ncell * rs);
+    L.fm = take(3 * ncell * rs);
+    L.frout = take(plane * rs);
+    L.ftend = take((size_t)g.n_r * g.n_phi * rs);
+    for (int q = 0; q < 2; ++q) L.tg[q] = take(plane * rs);
+  }
   L.total = off;
   return L;
 }
@@ -145,6 +153,7 @@ int validate(const icr_grid* g, const icr_phys* p) {
     return fail(ICR_ERR_ARG, "unknown limiter %d", p->limiter);
   if (p->precision != ICR_PREC_F64 && p->precision != ICR_PREC_F32)
     return fail(ICR_ERR_ARG, "precision must be 64 or 32");
+  if (p->tracer != 0 && p->tracer != 1) return fail(ICR_ERR_ARG, "tracer must be 0 or 1");
   return ICR_OK;
 }
 
@@ -169,6 +178,9 @@ struct icr_solver {
   bool graphs_ok;
 
   void* u(int q) { return ws + L.u[q]; }
+  bool trc() const { return p.tracer != 0; }
+  void* tr(int q) { return trc() ? ws + L.t[q] : nullptr; }
+  void* tg(int q) { return trc() ? ws + L.tg[q] : nullptr; }
   void* ghost(int q) { return ws + L.g[q]; }
   double* m64() { return (double*)(ws + L.m64); }
   void* mr() { return ws + L.mr; }
@@ -226,6 +238,31 @@ struct icr_solver {
     a.cfl = p.cfl;
     a.gravity = p.gravity ? 1 : 0;
     a.corot = p.corotation ? 1 : 0;
+    a.fmass = trc() ? (R*)(ws + L.fm) : nullptr;
+    a.fmass_rout = trc() ? (R*)(ws + L.frout) : nullptr;
+    a.fmass_tend = trc() ? (R*)(ws + L.ftend) : nullptr;
+    return a;
+  }
+
+  // tracer stage: rho tau from buffer tin (density of state uin), combine
+  // with tn in stage 2, into tout; inner ghost tau gh
+  template <typename R>
+  TracerArgs<R> tracer_args(int tin, int uin, int tn, int tout, int gh) {
+    TracerArgs<R> a;
+    a.tin = (const R*)tr(tin);
+    a.tn = (const R*)tr(tn);
+    a.tout = (R*)tr(tout);
+    a.rho = (const R*)u(uin);  // variable 0 of the state is rho
+    a.fm = (const R*)(ws + L.fm);
+    a.frout = (const R*)(ws + L.frout);
+    a.ftend = (const R*)(ws + L.ftend);
+    a.gtau = (const R*)tg(gh);
+    a.m = metric_view<R>((const R*)mr(), g.n_r, g.n_theta, (g.th_max - g.th_min) / g.n_theta);
+    a.clock = clock();
+    a.nr = g.n_r;
+    a.nt = g.n_theta;
+    a.np = g.n_phi;
+    a.ncell = ncell();
     return a;
   }
 
@@ -253,15 +290,17 @@ struct icr_solver {
   void enqueue_stages(int from, int to, hipStream_t st, hipEvent_t* ev) {
     const StageArgs<R> a1 = stage_args<R>(from, from, 2, 0);
     const StageArgs<R> a2 = stage_args<R>(2, from, to, 1);
-    if (variant == 1) {
+    if (variant == 1)
       launch_stage<R>(a1, 1, p.flux, p.limiter, grid(), block(), st);
-      if (ev) (void)hipEventRecord(ev[2], st);
-      launch_stage<R>(a2, 2, p.flux, p.limiter, grid(), block(), st);
-    } else {
+    else
       launch_stage_lds<R>(a1, 1, p.flux, p.limiter, tile_r, planes, st);
-      if (ev) (void)hipEventRecord(ev[2], st);
+    if (trc()) launch_tracer<R>(tracer_args<R>(from, from, from, 2, 0), 1, st);
+    if (ev) (void)hipEventRecord(ev[2], st);
+    if (variant == 1)
+      launch_stage<R>(a2, 2, p.flux, p.limiter, grid(), block(), st);
+    else
       launch_stage_lds<R>(a2, 2, p.flux, p.limiter, tile_r, planes, st);
-    }
+    if (trc()) launch_tracer<R>(tracer_args<R>(2, 2, from, to, 1), 2, st);
     if (ev) (void)hipEventRecord(ev[3], st);
     launch_finalize<R>(clock(), (const double*)(ws + L.partials), stage_blocks(), p.cfl, 1,
                        logging() ? 1 : 0, probe_args(), u(to), (double*)(ws + L.plog), st);
@@ -273,7 +312,7 @@ struct icr_solver {
   void enqueue_step(int from, hipStream_t st, hipEvent_t* ev = nullptr) {
     const int to = from ^ 1;
     if (ev) (void)hipEventRecord(ev[0], st);
-    launch_boundary(bnd(), clock(), ghost(0), ghost(1), f32, st);
+    launch_boundary(bnd(), clock(), ghost(0), ghost(1), tg(0), tg(1), f32, st);
     if (ev) (void)hipEventRecord(ev[1], st);
     if (f32)
       enqueue_stages<float>(from, to, st, ev);
@@ -550,6 +589,8 @@ int icr_init_radial(icr_solver* s) {
     launch_init_radial<double>(s->bnd(), s->m64(), s->u(s->cur), s->g.n_r, s->p.gamma,
                                s->stream);
   HIP_TRY(hipGetLastError());
+  if (s->trc())
+    HIP_TRY(hipMemsetAsync(s->tr(s->cur), 0, (s->f32 ? 4 : 8) * (size_t)s->ncell(), s->stream));
   DevClock c;
   int rc = s->read_clock(&c);
   if (rc) return rc;
@@ -587,6 +628,8 @@ int icr_set_state(icr_solver* s, const double* data, int kind, int on_device) {
     launch_import<float>(src, s->u(s->cur), n, kind, s->un.scale(), s->p.gamma, s->stream);
   else
     launch_import<double>(src, s->u(s->cur), n, kind, s->un.scale(), s->p.gamma, s->stream);
+  if (s->trc())
+    (void)hipMemsetAsync(s->tr(s->cur), 0, (s->f32 ? 4 : 8) * (size_t)n, s->stream);
   hipError_t e = hipStreamSynchronize(s->stream);
   if (tmp) (void)hipFree(tmp);
   if (e != hipSuccess) return fail(ICR_ERR_HIP, "state import failed: %s", hipGetErrorString(e));
@@ -812,6 +855,86 @@ int icr_sample_shell(icr_solver* s, double r_m, double* out) {
   return ICR_OK;
 }
 
+int icr_set_tracer(icr_solver* s, const double* tau, int on_device) {
+  if (!s || !tau) return fail(ICR_ERR_ARG, "NULL argument");
+  if (!s->trc()) return fail(ICR_ERR_STATE, "solver created without the tracer");
+  if (!s->have_state) return fail(ICR_ERR_STATE, "set the state first");
+  const long long n = s->ncell();
+  double* src = (double*)tau;
+  double* tmp = nullptr;
+  if (!on_device) {
+    HIP_TRY(hipMalloc(&tmp, sizeof(double) * (size_t)n));
+    hipError_t e = hipMemcpyAsync(tmp, tau, sizeof(double) * (size_t)n, hipMemcpyHostToDevice,
+                                  s->stream);
+    if (e != hipSuccess) {
+      (void)hipFree(tmp);
+      return fail(ICR_ERR_HIP, "copy of the tracer failed: %s", hipGetErrorString(e));
+    }
+    src = tmp;
+  }
+  if (s->f32)
+    launch_tracer_io<float>(s->u(s->cur), s->tr(s->cur), src, n, 1, s->stream);
+  else
+    launch_tracer_io<double>(s->u(s->cur), s->tr(s->cur), src, n, 1, s->stream);
+  hipError_t e = hipStreamSynchronize(s->stream);
+  if (tmp) (void)hipFree(tmp);
+  if (e != hipSuccess) return fail(ICR_ERR_HIP, "tracer import failed: %s", hipGetErrorString(e));
+  return ICR_OK;
+}
+
+int icr_get_tracer(icr_solver* s, double* tau, int on_device) {
+  if (!s || !tau) return fail(ICR_ERR_ARG, "NULL argument");
+  if (!s->trc()) return fail(ICR_ERR_STATE, "solver created without the tracer");
+  if (!s->have_state) return fail(ICR_ERR_STATE, "no state yet");
+  const long long n = s->ncell();
+  double* dst = tau;
+  double* tmp = nullptr;
+  if (!on_device) {
+    HIP_TRY(hipMalloc(&tmp, sizeof(double) * (size_t)n));
+    dst = tmp;
+  }
+  if (s->f32)
+    launch_tracer_io<float>(s->u(s->cur), s->tr(s->cur), dst, n, 0, s->stream);
+  else
+    launch_tracer_io<double>(s->u(s->cur), s->tr(s->cur), dst, n, 0, s->stream);
+  hipError_t e = hipSuccess;
+  if (tmp) e = hipMemcpyAsync(tau, tmp, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost,
+                              s->stream);
+  hipError_t e2 = hipStreamSynchronize(s->stream);
+  if (tmp) (void)hipFree(tmp);
+  if (e != hipSuccess || e2 != hipSuccess)
+    return fail(ICR_ERR_HIP, "tracer export failed: %s",
+                hipGetErrorString(e != hipSuccess ? e : e2));
+  return ICR_OK;
+}
+
+int icr_divv(icr_solver* s, double* out, int on_device) {
+  if (!s || !out) return fail(ICR_ERR_ARG, "NULL argument");
+  if (!s->have_state || !s->have_maps) return fail(ICR_ERR_STATE, "maps and state first");
+  const long long n = s->ncell();
+  double* dst = out;
+  double* tmp = nullptr;
+  if (!on_device) {
+    HIP_TRY(hipMalloc(&tmp, sizeof(double) * (size_t)n));
+    dst = tmp;
+  }
+  const double inv_t = 1.0 / s->un.t;
+  if (s->f32)
+    launch_divv<float>(s->stage_args<float>(s->cur, s->cur, s->cur, 0), s->bnd(), inv_t, dst,
+                       s->stream);
+  else
+    launch_divv<double>(s->stage_args<double>(s->cur, s->cur, s->cur, 0), s->bnd(), inv_t, dst,
+                        s->stream);
+  hipError_t e = hipGetLastError();
+  if (tmp && e == hipSuccess)
+    e = hipMemcpyAsync(out, tmp, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost, s->stream);
+  hipError_t e2 = hipStreamSynchronize(s->stream);
+  if (tmp) (void)hipFree(tmp);
+  if (e != hipSuccess || e2 != hipSuccess)
+    return fail(ICR_ERR_HIP, "divergence failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+  return ICR_OK;
+}
+
 int icr_profile_steps(icr_solver* s, int n, double* avg_ms) {
   if (!s || !avg_ms) return fail(ICR_ERR_ARG, "NULL argument");
   if (n < 1) return fail(ICR_ERR_ARG, "n_steps must be >= 1");
@@ -851,6 +974,7 @@ int icr_set_launch(icr_solver* s, int variant, int tile_r, int planes, int use_g
   if (planes == 0) planes = 8;
   if (planes < 1 || planes > s->g.n_phi)
     return fail(ICR_ERR_ARG, "planes must be in [1, n_phi] (got %d)", planes);
+  if (variant == 2 && s->trc()) tile_r = 64;  // the tracer's flux stores exist for 64 x 4
   s->variant = variant;
   s->tile_r = tile_r;
   s->planes = planes;
@@ -979,6 +1103,8 @@ extern "C" {
 
 int icr_ens_workspace_bytes(int n, const icr_grid* grids, const icr_phys* phys, size_t* bytes) {
   if (n < 1 || !grids || !bytes) return fail(ICR_ERR_ARG, "need n >= 1, grids and bytes");
+  if (phys && phys->tracer)
+    return fail(ICR_ERR_UNSUPPORTED, "the passive tracer is available for single solvers only");
   size_t total = ens_table_bytes(n);
   for (int r = 0; r < n; ++r) {
     int rc = validate(&grids[r], phys);

@@ -94,16 +94,22 @@ void launch_metric(const MetricArgs& a, void* mr, bool f32, hipStream_t s) {
 // ------------------------------------------------------------- boundary --
 template <typename R>
 __global__ void k_boundary(BndArgs a, const DevClock* __restrict__ ck, R* __restrict__ g1,
-                           R* __restrict__ g2) {
+                           R* __restrict__ g2, R* __restrict__ tg1, R* __restrict__ tg2) {
   const int q = blockIdx.x * blockDim.x + threadIdx.x;
   const int plane = a.nt * a.np;
   if (q >= plane || !ck->active) return;
   const int j = q % a.nt, k = q / a.nt;
   double w[NV];
-  boundary_prim(a, ck->t, j, k, w);
+  int in1, in2;
+  boundary_prim(a, ck->t, j, k, w, &in1);
   for (int v = 0; v < NV; ++v) g1[(long long)v * plane + q] = (R)w[v];
-  boundary_prim(a, ck->t + ck->dt, j, k, w);
+  boundary_prim(a, ck->t + ck->dt, j, k, w, &in2);
   for (int v = 0; v < NV; ++v) g2[(long long)v * plane + q] = (R)w[v];
+  // tracer of the inner ghost cells: CME material inside an inserted cone
+  if (tg1) {
+    tg1[q] = (R)in1;
+    tg2[q] = (R)in2;
+  }
 }
 
 // Boundary at an arbitrary time into a [8][nt][np] double buffer (SI).
@@ -117,14 +123,16 @@ __global__ void k_boundary_at(BndArgs a, double t, double* __restrict__ out, Sca
   for (int v = 0; v < NV; ++v) out[(long long)v * plane + q] = w[v] * sc.s[v];
 }
 
-void launch_boundary(const BndArgs& a, const DevClock* ck, void* g1, void* g2, bool f32,
-                     hipStream_t s) {
+void launch_boundary(const BndArgs& a, const DevClock* ck, void* g1, void* g2, void* tg1,
+                     void* tg2, bool f32, hipStream_t s) {
   const int plane = a.nt * a.np;
   const dim3 grid((plane + 255) / 256), blk(256);
   if (f32)
-    hipLaunchKernelGGL(k_boundary<float>, grid, blk, 0, s, a, ck, (float*)g1, (float*)g2);
+    hipLaunchKernelGGL(k_boundary<float>, grid, blk, 0, s, a, ck, (float*)g1, (float*)g2,
+                       (float*)tg1, (float*)tg2);
   else
-    hipLaunchKernelGGL(k_boundary<double>, grid, blk, 0, s, a, ck, (double*)g1, (double*)g2);
+    hipLaunchKernelGGL(k_boundary<double>, grid, blk, 0, s, a, ck, (double*)g1, (double*)g2,
+                       (double*)tg1, (double*)tg2);
 }
 
 void launch_boundary_at(const BndArgs& a, double t, double* out, const Scale& sc, hipStream_t s) {
@@ -199,6 +207,10 @@ __global__ void __launch_bounds__(256) k_stage_v1(StageArgs<R> a) {
         const R rm2 = a.m.rm2[i], rp2 = a.m.rp2[i], ivr = a.m.ivr[i];
 #pragma unroll
         for (int v = 0; v < NV; ++v) L[v] -= (rp2 * fp[v] - rm2 * fm[v]) * ivr;
+        if (a.fmass) {
+          a.fmass[c] = fm[0];
+          if (i == a.nr - 1) a.fmass_rout[(long long)k * a.nt + j] = fp[0];
+        }
       }
       const R hr = a.m.hr[i];
       {  // theta faces, mirror rows beyond the (reflecting) colatitude edges
@@ -221,6 +233,10 @@ __global__ void __launch_bounds__(256) k_stage_v1(StageArgs<R> a) {
         const R sm = a.m.sm[j], sp = a.m.sp[j], ict = a.m.ict[j];
 #pragma unroll
         for (int v = 0; v < NV; ++v) L[v] -= hr * (sp * fp[v] - sm * fm[v]) * ict;
+        if (a.fmass) {
+          a.fmass[a.ncell + c] = fm[0];
+          if (j == a.nt - 1) a.fmass_tend[(long long)k * a.nr + i] = fp[0];
+        }
       }
       {  // phi faces, periodic
         R w0[NV], w1[NV], w3[NV], w4[NV], wl[NV], wr[NV], fm[NV], fp[NV];
@@ -238,6 +254,7 @@ __global__ void __launch_bounds__(256) k_stage_v1(StageArgs<R> a) {
         const R f = hr * a.m.phf[j];
 #pragma unroll
         for (int v = 0; v < NV; ++v) L[v] -= f * (fp[v] - fm[v]);
+        if (a.fmass) a.fmass[2 * a.ncell + c] = fm[0];
       }
       add_sources<R>(wc, a.m, i, j, a.omega, a.gravity, a.corot, L);
       R uc[NV];
@@ -466,6 +483,142 @@ template void launch_shell<double>(const void*, const double*, int, int, int, do
                                    const Scale&, double*, hipStream_t);
 template void launch_shell<float>(const void*, const double*, int, int, int, double, double,
                                   const Scale&, double*, hipStream_t);
+
+// ---------------------------------------------------- passive tracer --
+// rho tau of every cell, one RK stage: the face flux is the stage's mass flux
+// times tau = (rho tau) / rho of the upwind cell (the inner ghost carries 1
+// inside an inserted CME cone, 0 elsewhere; beyond r_out and the colatitude
+// edges the edge cell's own tau; periodic in phi), divergence with the same
+// metric factors as the stage kernels, then the stage's RK combine.
+template <typename R, int STAGE>
+__global__ void __launch_bounds__(256) k_tracer(TracerArgs<R> a) {
+  const long long c =
+      (long long)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (c >= a.ncell) return;
+  const int nr = a.nr, nt = a.nt, np = a.np;
+  const int i = (int)(c % nr);
+  const long long col = c / nr;
+  const int j = (int)(col % nt), k = (int)(col / nt);
+  if (!a.clock->active) {
+    if (STAGE == 2) a.tout[c] = a.tn[c];
+    return;
+  }
+  const long long n = a.ncell, pc = (long long)nt * nr;
+  auto tau = [&](long long q) { return a.tin[q] / a.rho[q]; };
+  const R tc = tau(c);
+  // r faces i-1/2, i+1/2
+  const R fr0 = a.fm[c];
+  const R fr1 = i + 1 < nr ? a.fm[c + 1] : a.frout[(long long)k * nt + j];
+  const R tr0 = i > 0 ? tau(c - 1) : a.gtau[(long long)k * nt + j];
+  const R tr1 = i + 1 < nr ? tau(c + 1) : tc;
+  const R gr0 = fr0 * (fr0 >= R(0) ? tr0 : tc), gr1 = fr1 * (fr1 >= R(0) ? tc : tr1);
+  // theta faces j-1/2, j+1/2
+  const R ft0 = a.fm[n + c];
+  const R ft1 = j + 1 < nt ? a.fm[n + c + nr] : a.ftend[(long long)k * nr + i];
+  const R tt0 = j > 0 ? tau(c - nr) : tc;
+  const R tt1 = j + 1 < nt ? tau(c + nr) : tc;
+  const R gt0 = ft0 * (ft0 >= R(0) ? tt0 : tc), gt1 = ft1 * (ft1 >= R(0) ? tc : tt1);
+  // phi faces k-1/2, k+1/2 (periodic)
+  const long long cm = c + (k > 0 ? -pc : (long long)(np - 1) * pc);
+  const long long cp = c + (k + 1 < np ? pc : -(long long)(np - 1) * pc);
+  const R fp0 = a.fm[2 * n + c], fp1 = a.fm[2 * n + cp];
+  const R gp0 = fp0 * (fp0 >= R(0) ? tau(cm) : tc), gp1 = fp1 * (fp1 >= R(0) ? tc : tau(cp));
+  const R hr = a.m.hr[i];
+  R L = R(0);
+  L -= (a.m.rp2[i] * gr1 - a.m.rm2[i] * gr0) * a.m.ivr[i];
+  L -= hr * (a.m.sp[j] * gt1 - a.m.sm[j] * gt0) * a.m.ict[j];
+  L -= hr * a.m.phf[j] * (gp1 - gp0);
+  const R dt = (R)a.clock->dt;
+  if (STAGE == 1)
+    a.tout[c] = a.tin[c] + dt * L;
+  else
+    a.tout[c] = R(0.5) * a.tn[c] + R(0.5) * (a.tin[c] + dt * L);
+}
+
+template <typename R>
+void launch_tracer(const TracerArgs<R>& a, int stage, hipStream_t s) {
+  const dim3 grid((unsigned)((a.ncell + 255) / 256)), blk(256);
+  if (stage == 1)
+    hipLaunchKernelGGL((k_tracer<R, 1>), grid, blk, 0, s, a);
+  else
+    hipLaunchKernelGGL((k_tracer<R, 2>), grid, blk, 0, s, a);
+}
+template void launch_tracer<double>(const TracerArgs<double>&, int, hipStream_t);
+template void launch_tracer<float>(const TracerArgs<float>&, int, hipStream_t);
+
+template <typename R>
+__global__ void k_tracer_io(const R* __restrict__ u, R* __restrict__ t, double* __restrict__ tau,
+                            long long n, int to_state) {
+  const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n) return;
+  if (to_state)
+    t[c] = u[c] * (R)tau[c];
+  else
+    tau[c] = (double)(t[c] / u[c]);
+}
+
+template <typename R>
+void launch_tracer_io(const void* u, void* t, double* tau, long long n, int to_state,
+                      hipStream_t s) {
+  hipLaunchKernelGGL(k_tracer_io<R>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
+                     (const R*)u, (R*)t, tau, n, to_state);
+}
+template void launch_tracer_io<double>(const void*, void*, double*, long long, int, hipStream_t);
+template void launch_tracer_io<float>(const void*, void*, double*, long long, int, hipStream_t);
+
+// ------------------------------------------------- velocity divergence --
+// Finite-volume divergence of the co-rotating-frame velocity with face
+// velocities the mean of the two neighbouring cell centres (inner ghost from
+// the boundary primitives, zero-gradient beyond r_out, mirror rows with
+// v_theta negated beyond the colatitude edges, periodic phi), in 1/s.
+template <typename R>
+__global__ void __launch_bounds__(256) k_divv(StageArgs<R> a, BndArgs b, double inv_time,
+                                              double* out) {
+  const long long c =
+      (long long)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
+  if (c >= a.ncell) return;
+  const int nr = a.nr, nt = a.nt, np = a.np;
+  const int i = (int)(c % nr);
+  const long long col = c / nr;
+  const int j = (int)(col % nt), k = (int)(col / nt);
+  R w0[NV], wm[NV], wp[NV];
+  load_prim(a, i, j, k, w0);
+  if (i > 0) {
+    load_prim(a, i - 1, j, k, wm);
+  } else {  // inner ghost: the boundary primitives at the current time
+    double wb[NV];
+    boundary_prim(b, a.clock->t, j, k, wb);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) wm[v] = (R)wb[v];
+  }
+  load_prim(a, i + 1, j, k, wp);
+  const R vr0 = R(0.5) * (wm[1] + w0[1]), vr1 = R(0.5) * (w0[1] + wp[1]);
+  bool fm, fp;
+  load_prim(a, i, mirror_row(j - 1, nt, fm), k, wm);
+  load_prim(a, i, mirror_row(j + 1, nt, fp), k, wp);
+  if (fm) flip_theta(wm);
+  if (fp) flip_theta(wp);
+  const R vt0 = R(0.5) * (wm[2] + w0[2]), vt1 = R(0.5) * (w0[2] + wp[2]);
+  load_prim(a, i, j, (k + np - 1) % np, wm);
+  load_prim(a, i, j, (k + 1) % np, wp);
+  const R vp0 = R(0.5) * (wm[3] + w0[3]), vp1 = R(0.5) * (w0[3] + wp[3]);
+  const R hr = a.m.hr[i];
+  const R d = (a.m.rp2[i] * vr1 - a.m.rm2[i] * vr0) * a.m.ivr[i] +
+              hr * (a.m.sp[j] * vt1 - a.m.sm[j] * vt0) * a.m.ict[j] +
+              hr * a.m.phf[j] * (vp1 - vp0);
+  out[c] = (double)d * inv_time;
+}
+
+template <typename R>
+void launch_divv(const StageArgs<R>& a, const BndArgs& b, double inv_time_unit, double* out,
+                 hipStream_t s) {
+  hipLaunchKernelGGL(k_divv<R>, dim3((unsigned)((a.ncell + 255) / 256)), dim3(256), 0, s, a, b,
+                     inv_time_unit, out);
+}
+template void launch_divv<double>(const StageArgs<double>&, const BndArgs&, double, double*,
+                                  hipStream_t);
+template void launch_divv<float>(const StageArgs<float>&, const BndArgs&, double, double*,
+                                 hipStream_t);
 
 template <typename R>
 __global__ void k_probe_sample(ProbeArgs a, const DevClock* __restrict__ ck,

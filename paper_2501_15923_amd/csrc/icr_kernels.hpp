@@ -64,6 +64,29 @@ struct StageArgs {
   R gam, gm1, igm1, omega;
   double cfl;
   int gravity, corot;
+  // optional (passive tracer on): face mass fluxes of this stage, the lower
+  // r / theta / phi face of every cell [3][ncell], the outer r face [np][nt]
+  // and the upper theta face of the last row [np][nr]
+  R* __restrict__ fmass;
+  R* __restrict__ fmass_rout;
+  R* __restrict__ fmass_tend;
+};
+
+// Passive tracer stage: rho tau advected with the stage's mass fluxes.
+template <typename R>
+struct TracerArgs {
+  const R* __restrict__ tin;   // rho tau the stage starts from
+  const R* __restrict__ tn;    // rho tau at t^n (stage-2 combine)
+  R* __restrict__ tout;
+  const R* __restrict__ rho;   // density the stage starts from (stride 1)
+  const R* __restrict__ fm;    // [3][ncell] lower-face mass fluxes
+  const R* __restrict__ frout; // [np][nt]
+  const R* __restrict__ ftend; // [np][nr]
+  const R* __restrict__ gtau;  // [np][nt] tau of the inner ghost cells
+  Metric<R> m;
+  const DevClock* clock;
+  int nr, nt, np;
+  long long ncell;
 };
 
 struct ProbeArgs {
@@ -81,6 +104,16 @@ struct ProbeArgs {
 
 
 // ------------------------------------------------------ shared helpers --
+constexpr int NXCD = 8;  // accelerator complex dies of MI355X
+
+// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
+// L2): remap workgroup b of nb so that XCD x gets a contiguous range of
+// tiles / cells, and neighbours that share data run on the same L2.
+__device__ __forceinline__ int xcd_tile(int b, int nb) {
+  const int xcd = b % NXCD, per = nb / NXCD, rem = nb % NXCD;
+  return xcd * per + (xcd < rem ? xcd : rem) + b / NXCD;
+}
+
 // Block of 256 threads: max of lam, sums of s1/s0 (fixed tree), min of bad.
 __device__ __forceinline__ void block_reduce(double& lam, double& s1, double& s0, int& bad,
                                              double (*sh)[4]) {
@@ -235,8 +268,11 @@ __device__ inline void probe_eval(const ProbeArgs& a, const R* __restrict__ u, i
   for (int v = 0; v < NV; ++v) o[4 + v] = acc[v] * a.sc.s[v];
 }
 
-// Primitive at the inner shell for column (j, k) at code time t.
-__device__ inline void boundary_prim(const BndArgs& a, double t, int j, int k, double (&w)[NV]) {
+// Primitive at the inner shell for column (j, k) at code time t; *inside
+// (optional) is set to 1 when a cone CME is being inserted there.
+__device__ inline void boundary_prim(const BndArgs& a, double t, int j, int k, double (&w)[NV],
+                                     int* inside = nullptr) {
+  if (inside) *inside = 0;
   const long long plane = (long long)a.nt * a.np;
   const long long q = (long long)j * a.np + k;
   const int n = a.n_maps;
@@ -266,6 +302,7 @@ __device__ inline void boundary_prim(const BndArgs& a, double t, int j, int k, d
       if (!(t >= m[0] && t < m[0] + m[1])) continue;
       const double cosd = cth * cos(m[2]) + sth * sin(m[2]) * cos(ph - m[3]);
       if (cosd >= m[4]) {
+        if (inside) *inside = 1;
         w[0] = m[6];
         w[1] = m[5];
         w[2] = 0.0;
@@ -280,7 +317,8 @@ template <typename R>
 Metric<R> metric_view(const R* base, int nr, int nt, double dth);
 
 void launch_metric(const MetricArgs& a, void* mr, bool f32, hipStream_t s);
-void launch_boundary(const BndArgs& a, const DevClock* ck, void* g1, void* g2, bool f32,
+void launch_boundary(const BndArgs& a, const DevClock* ck, void* g1, void* g2, void* tg1,
+                     void* tg2, bool f32,
                      hipStream_t s);
 void launch_boundary_at(const BndArgs& a, double t, double* out, const Scale& sc, hipStream_t s);
 void launch_clock_begin(DevClock* ck, double t_end, hipStream_t s);
@@ -301,6 +339,18 @@ void launch_export(const void* u, double* out, long long n, int kind, const Scal
 template <typename R>
 void launch_probe_sample(const ProbeArgs& a, const DevClock* ck, const void* u, double* out,
                          hipStream_t s);
+template <typename R>
+void launch_tracer(const TracerArgs<R>& a, int stage, hipStream_t s);
+// tau [np][nt][nr] (host layout, device memory) <-> rho tau, with rho the
+// density of state u
+template <typename R>
+void launch_tracer_io(const void* u, void* t, double* tau, long long n, int to_state,
+                      hipStream_t s);
+// velocity divergence [1/s] of state a.uin; inner ghost from the boundary
+// maps / CMEs at the clock's time
+template <typename R>
+void launch_divv(const StageArgs<R>& a, const BndArgs& b, double inv_time_unit, double* out,
+                 hipStream_t s);
 template <typename R>
 void launch_shell(const void* u, const double* rc, int nr, int nt, int np, double r, double gam,
                   const Scale& sc, double* out, hipStream_t s);

@@ -8,15 +8,7 @@ namespace icr {
 #define ICR_LDS_WAVES 2
 #endif
 
-// Workgroups are dispatched round-robin over the 8 XCDs (each with its own
-// L2): XCD x gets a contiguous range of tiles (r fastest, then theta, then
-// phi) so that tiles sharing halos run on the same L2.
-__device__ __forceinline__ int xcd_tile(int b, int nb) {
-  const int xcd = b % NXCD, per = nb / NXCD, rem = nb % NXCD;
-  return xcd * per + (xcd < rem ? xcd : rem) + b / NXCD;
-}
-
-template <typename R, int TR, int TT, int FLUX, int LIM, int STAGE>
+template <typename R, int TR, int TT, int FLUX, int LIM, int STAGE, bool FM>
 __global__ void __launch_bounds__(TR* TT) __attribute__((amdgpu_waves_per_eu(ICR_LDS_WAVES)))
 k_stage_lds(StageArgs<R> a, int kplanes) {
   const int nbx = gridDim.x, nby = gridDim.y;
@@ -24,39 +16,47 @@ k_stage_lds(StageArgs<R> a, int kplanes) {
   const int b = (blockIdx.z * nby + blockIdx.y) * nbx + blockIdx.x;
   const int tile = xcd_tile(b, nb);
   __shared__ StageSmem<R, TR, TT> sm;
-  stage_tile<R, TR, TT, FLUX, LIM, STAGE>(a, kplanes, tile % nbx, (tile / nbx) % nby,
-                                          tile / (nbx * nby), tile, sm);
+  stage_tile<R, TR, TT, FLUX, LIM, STAGE, FM>(a, kplanes, tile % nbx, (tile / nbx) % nby,
+                                              tile / (nbx * nby), tile, sm);
 }
 
-template <typename R, int TR, int TT, int FLUX, int LIM>
+template <typename R, int TR, int TT, int FLUX, int LIM, bool FM>
 static void launch_lds_t(const StageArgs<R>& a, int stage, int kplanes, hipStream_t s) {
   const dim3 grid((a.nr + TR - 1) / TR, (a.nt + TT - 1) / TT, (a.np + kplanes - 1) / kplanes);
   const dim3 blk(TR, TT);
   if (stage == 1)
-    hipLaunchKernelGGL((k_stage_lds<R, TR, TT, FLUX, LIM, 1>), grid, blk, 0, s, a, kplanes);
+    hipLaunchKernelGGL((k_stage_lds<R, TR, TT, FLUX, LIM, 1, FM>), grid, blk, 0, s, a, kplanes);
   else
-    hipLaunchKernelGGL((k_stage_lds<R, TR, TT, FLUX, LIM, 2>), grid, blk, 0, s, a, kplanes);
+    hipLaunchKernelGGL((k_stage_lds<R, TR, TT, FLUX, LIM, 2, FM>), grid, blk, 0, s, a, kplanes);
 }
 
-template <typename R, int TR, int TT>
+template <typename R, int TR, int TT, bool FM>
 static void launch_lds_tile(const StageArgs<R>& a, int stage, int flux, int lim, int kplanes,
                             hipStream_t s) {
   if (flux == FLUX_TVDLF) {
-    if (lim == LIM_MINMOD) launch_lds_t<R, TR, TT, FLUX_TVDLF, LIM_MINMOD>(a, stage, kplanes, s);
-    else launch_lds_t<R, TR, TT, FLUX_TVDLF, LIM_MC>(a, stage, kplanes, s);
+    if (lim == LIM_MINMOD)
+      launch_lds_t<R, TR, TT, FLUX_TVDLF, LIM_MINMOD, FM>(a, stage, kplanes, s);
+    else
+      launch_lds_t<R, TR, TT, FLUX_TVDLF, LIM_MC, FM>(a, stage, kplanes, s);
   } else {
-    if (lim == LIM_MINMOD) launch_lds_t<R, TR, TT, FLUX_HLL, LIM_MINMOD>(a, stage, kplanes, s);
-    else launch_lds_t<R, TR, TT, FLUX_HLL, LIM_MC>(a, stage, kplanes, s);
+    if (lim == LIM_MINMOD)
+      launch_lds_t<R, TR, TT, FLUX_HLL, LIM_MINMOD, FM>(a, stage, kplanes, s);
+    else
+      launch_lds_t<R, TR, TT, FLUX_HLL, LIM_MC, FM>(a, stage, kplanes, s);
   }
 }
 
+// With the passive tracer (a.fmass set) only the 64 x 4 tile is built with
+// the mass-flux stores; the solver keeps tile_r = 64 in that case.
 template <typename R>
 void launch_stage_lds(const StageArgs<R>& a, int stage, int flux, int lim, int tile_r,
                       int kplanes, hipStream_t s) {
-  if (tile_r == 32)
-    launch_lds_tile<R, 32, 8>(a, stage, flux, lim, kplanes, s);
+  if (a.fmass)
+    launch_lds_tile<R, 64, 4, true>(a, stage, flux, lim, kplanes, s);
+  else if (tile_r == 32)
+    launch_lds_tile<R, 32, 8, false>(a, stage, flux, lim, kplanes, s);
   else
-    launch_lds_tile<R, 64, 4>(a, stage, flux, lim, kplanes, s);
+    launch_lds_tile<R, 64, 4, false>(a, stage, flux, lim, kplanes, s);
 }
 template void launch_stage_lds<double>(const StageArgs<double>&, int, int, int, int, int,
                                        hipStream_t);

@@ -21,7 +21,6 @@
 
 namespace icr {
 
-constexpr int NXCD = 8;  // accelerator complex dies of MI355X
 
 template <typename R, bool FAST>
 __device__ __forceinline__ void load_cons_prim(const StageArgs<R>& a, long long c, R (&w)[NV]) {
@@ -61,7 +60,9 @@ struct StageSmem {
   R sFt[NV][TT + 1][TR];
 };
 
-template <typename R, int TR, int TT, int FLUX, int LIM, int STAGE>
+// FM: also store the stage's face mass fluxes (a.fmass, passive tracer on);
+// a compile-time switch so that the default kernel carries no trace of it.
+template <typename R, int TR, int TT, int FLUX, int LIM, int STAGE, bool FM = false>
 __device__ __forceinline__ void stage_tile(const StageArgs<R>& a, int kplanes, int bx, int by,
                                            int bz, int pslot, StageSmem<R, TR, TT>& sm) {
   constexpr int NT = TR * TT;
@@ -223,6 +224,13 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R>& a, int kplanes, i
         add_sources<R>(wa, a.m, ic, jc, a.omega, a.gravity, a.corot, L);
         const R dt = (R)a.clock->dt;
         const long long c = kbase + colbase;
+        if constexpr (FM) {  // passive tracer on: keep this stage's mass fluxes
+          a.fmass[c] = sFr[0][tj][ti];
+          a.fmass[a.ncell + c] = sFt[0][tj][ti];
+          a.fmass[2 * a.ncell + c] = fcar[0];
+          if (i == nr - 1) a.fmass_rout[(long long)k * nt + j] = sFr[0][tj][ti + 1];
+          if (j == nt - 1) a.fmass_tend[(long long)k * nr + i] = sFt[0][tj + 1][ti];
+        }
         if (STAGE == 1) {
 #pragma unroll
           for (int v = 0; v < NV; ++v) a.uout[v * a.ncell + c] = uc[v] + dt * L[v];

@@ -26,15 +26,17 @@ def make_grid(grid: Grid, max_maps=16, max_cmes=4, max_probes=8, max_traj_pts=10
 
 
 def make_phys(gamma=1.5, omega=OMEGA_SUN, cfl=0.4, flux=_abi.FLUX_TVDLF,
-              limiter=_abi.LIM_MINMOD, precision=64, gravity=True, corotation=True):
+              limiter=_abi.LIM_MINMOD, precision=64, gravity=True, corotation=True,
+              tracer=False):
     return _abi.IcrPhys(gamma, omega, cfl, flux, limiter, precision, int(gravity),
-                        int(corotation))
+                        int(corotation), int(tracer))
 
 
 class Solver:
     def __init__(self, grid: Grid, *, gamma=1.5, omega=OMEGA_SUN, cfl=0.4,
                  flux=_abi.FLUX_TVDLF, limiter=_abi.LIM_MINMOD, precision=64,
-                 gravity=True, corotation=True, max_maps=16, max_cmes=4, max_probes=8,
+                 gravity=True, corotation=True, tracer=False, max_maps=16, max_cmes=4,
+                 max_probes=8,
                  max_traj_pts=1024, probe_log_rows=0, device=0, stream=None):
         import torch
         self.torch = torch
@@ -42,7 +44,8 @@ class Solver:
         self.owned = True
         self.device = torch.device("cuda", device)
         self.g = make_grid(grid, max_maps, max_cmes, max_probes, max_traj_pts, probe_log_rows)
-        self.p = make_phys(gamma, omega, cfl, flux, limiter, precision, gravity, corotation)
+        self.p = make_phys(gamma, omega, cfl, flux, limiter, precision, gravity, corotation,
+                           tracer)
         nbytes = ctypes.c_size_t()
         check(lib().icr_workspace_bytes(ctypes.byref(self.g), ctypes.byref(self.p),
                                         ctypes.byref(nbytes)))
@@ -163,6 +166,25 @@ class Solver:
         n = ctypes.c_int()
         check(lib().icr_read_probe_log(self.h, _np_ptr(out), cap, ctypes.byref(n)))
         return out[:min(n.value, cap)], n.value
+
+    def set_tracer(self, tau):
+        """CME mass fraction tau [n_phi][n_theta][n_r] (scalar broadcasts)."""
+        if hasattr(tau, "data_ptr"):
+            check(lib().icr_set_tracer(self.h, _abi.dptr(tau.data_ptr()), 1))
+            return
+        tau = np.ascontiguousarray(np.broadcast_to(tau, self.shape[1:]), dtype=np.float64)
+        check(lib().icr_set_tracer(self.h, _np_ptr(tau), 0))
+
+    def get_tracer(self):
+        out = np.zeros(self.shape[1:])
+        check(lib().icr_get_tracer(self.h, _np_ptr(out), 0))
+        return out
+
+    def divv(self):
+        """Velocity divergence [1/s], [n_phi][n_theta][n_r]."""
+        out = np.zeros(self.shape[1:])
+        check(lib().icr_divv(self.h, _np_ptr(out), 0))
+        return out
 
     def shell(self, r):
         """rho and v_r on the sphere of radius r [m]: [2][n_theta][n_phi]."""

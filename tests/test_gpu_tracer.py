@@ -1,0 +1,140 @@
+"""GPU parity of the passive CME tracer and the velocity-divergence
+diagnostic (through the C-ABI) with the oracle.
+
+Workload: ragged 150 x 30 x 60 grid (not a multiple of the 64 x 4 tile),
+static relaxation map, a cone CME inserted from t = 0 so that CME material
+crosses several tiles; 40 steps.  Bars: the MHD state per the FP64 parity
+metric (1e-9), tau within 1e-9 absolute (tau is a mass fraction in [0, 1]),
+div V within 1e-9 of its largest magnitude.  The tracer must not feed back
+on the MHD state (bitwise), and graph replay must not change it (bitwise).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import parity
+from paper_2501_15923_amd import synth
+
+pytestmark = pytest.mark.gpu
+AU = synth.AU
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def mods():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import oracle
+    from paper_2501_15923_amd import _abi, solver
+    _abi.lib()
+    return oracle, solver, _abi
+
+
+G = synth.Grid(150, 30, 60)
+
+
+def cme_row():
+    earth = synth.orbit_table(3 * synth.DAY, 600.0, AU, 0.0, 0.4)
+    return synth.cone_cme(11, earth, t_start=0.0, duration=6 * synth.HOUR, speed=1100e3,
+                          half_width=35 * synth.DEG)
+
+
+def gpu(mods, steps, tracer=True, variant=2, graphs=1, precision=64):
+    _, solver, _ = mods
+    s = solver.Solver(G, tracer=tracer, precision=precision)
+    s.set_maps(np.zeros(1), synth.relax_map(G, 21)[None])
+    s.set_cmes(cme_row()[None])
+    s.init_radial()
+    s.set_launch(variant, 64, 8, graphs)
+    s.step(steps)
+    return s
+
+
+@pytest.fixture(scope="module")
+def orc_run(mods):
+    oracle = mods[0]
+    say("oracle: tracer run 150x30x60, 40 steps")
+    o = oracle.Oracle(G.nr, G.nt, G.np_, r_in=G.r_in, r_out=G.r_out, th_min=G.th_min,
+                      th_max=G.th_max, tracer=True)
+    o.set_maps(np.zeros(1), synth.relax_map(G, 21)[None])
+    o.set_cmes(cme_row()[None])
+    o.init_radial()
+    o.step(40)
+    return o
+
+
+@pytest.mark.parametrize("variant", [2, 1])
+def test_tracer_and_state_match_oracle(mods, orc_run, variant):
+    oracle = mods[0]
+    say(f"tracer parity, variant {variant}")
+    s = gpu(mods, 40, variant=variant)
+    parity.assert_parity(s.get_state(kind=1), orc_run.get_state(kind=oracle.CONS_CODE))
+    tg, to = s.get_tracer(), orc_run.get_tracer()
+    err = np.max(np.abs(tg - to))
+    say(f"  max |d tau| {err:.3e}, tau max {to.max():.3f}, cells with tau > 0.5: "
+        f"{int(np.sum(to > 0.5))}")
+    assert to.max() > 0.5 and np.sum(to > 0.5) > 20  # material crossed tile borders
+    assert err <= 1e-9
+    s.close()
+
+
+def test_tracer_does_not_feed_back_and_graphs_are_bitwise(mods):
+    say("tracer on/off, graphs on/off")
+    a = gpu(mods, 33, tracer=True, graphs=1)
+    b = gpu(mods, 33, tracer=False, graphs=1)
+    c = gpu(mods, 33, tracer=True, graphs=0)
+    assert np.array_equal(a.get_state(kind=1), b.get_state(kind=1))
+    assert np.array_equal(a.get_tracer(), c.get_tracer())
+    assert np.array_equal(a.get_state(kind=1), c.get_state(kind=1))
+    for x in (a, b, c):
+        x.close()
+
+
+def test_tracer_fp32_close_to_fp64(mods):
+    say("tracer fp32 vs fp64")
+    a = gpu(mods, 40, precision=64)
+    b = gpu(mods, 40, precision=32)
+    err = np.max(np.abs(a.get_tracer() - b.get_tracer()))
+    say(f"  max |d tau| {err:.3e}")
+    assert err < 1e-3
+    a.close()
+    b.close()
+
+
+def test_tracer_set_get_roundtrip_and_reset(mods):
+    _, solver, _ = mods
+    s = solver.Solver(G, tracer=True)
+    s.set_maps(np.zeros(1), synth.relax_map(G, 21)[None])
+    s.init_radial()
+    assert np.all(s.get_tracer() == 0.0)
+    rng = np.random.default_rng(3)
+    tau = rng.uniform(0, 1, s.shape[1:])
+    s.set_tracer(tau)
+    assert np.max(np.abs(s.get_tracer() - tau)) < 1e-15
+    s.set_state(s.get_state())
+    assert np.all(s.get_tracer() == 0.0)
+    s.close()
+
+
+def test_divv_matches_oracle(mods, orc_run):
+    say("div V parity")
+    s = gpu(mods, 40)
+    dg, do = s.divv(), orc_run.divv()
+    scale = np.max(np.abs(do))
+    err = np.max(np.abs(dg - do))
+    say(f"  max |d divV| {err:.3e} of {scale:.3e} 1/s")
+    assert scale > 0 and err <= 1e-9 * scale
+    s.close()
+
+
+def test_ensemble_rejects_tracer(mods):
+    _, _, abi = mods
+    from paper_2501_15923_amd.ensemble import Ensemble
+    with pytest.raises(abi.IcarusError) as e:
+        Ensemble([synth.Grid(64, 16, 32)], tracer=True)
+    assert e.value.code == abi.ICR_ERR_UNSUPPORTED
