@@ -49,9 +49,12 @@ def parse():
     ap.add_argument("--ingest-counters", nargs=4, default=None,
                     metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
                     help="write the --traffic file from four rocprofv3 --pmc output folders")
-    ap.add_argument("--workload", default="prod", choices=("prod", "ensemble", "relax"),
+    ap.add_argument("--workload", default="prod",
+                    choices=("prod", "ensemble", "relax", "jupiter"),
                     help="prod: 600x60x120 dynamic run (the headline line); ensemble: 64 "
-                         "uneven runs in one persistent launch vs 64 sequential runs")
+                         "runs batched vs the same runs one after the other; relax: warm vs "
+                         "plain relaxation on held-out maps; jupiter: 5.5 AU domain with "
+                         "hourly maps streamed into a 4-map buffer")
     ap.add_argument("--runs", type=int, default=64)
     ap.add_argument("--maps", type=int, default=4, help="held-out maps for --workload relax")
     ap.add_argument("--tracer", action="store_true",
@@ -205,6 +208,71 @@ def relax_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def jupiter_bench(args):
+    """Extended domain to 5.5 AU (803 x 60 x 120 cells), hourly maps streamed
+    into a 4-map buffer while the run advances (appends inside the timed
+    region), 4 probes including Jupiter's orbit."""
+    import torch
+
+    from paper_2501_15923_amd import _abi, configs
+    from paper_2501_15923_amd.solver import Solver
+
+    w = configs.jupiter_dynamic(days=1.0)
+    g = w.grid
+    log(f"bench: workload {w.name}, fp{args.precision}, {len(w.times)} maps streamed, "
+        f"steps {args.steps}, warmup {args.warmup}")
+    s = Solver(g, precision=args.precision, max_maps=4, probe_log_rows=args.steps + args.warmup + 16,
+               max_traj_pts=w.probes.shape[1])
+    s.set_maps(w.times[:3], w.maps[:3])
+    s.set_probes(w.probes, cadence=600.0)
+    s.init_radial()
+    nxt = [3]
+    appends = [0]
+
+    def feed():
+        while nxt[0] < len(w.times):
+            try:
+                s.append_maps(w.times[nxt[0]:nxt[0] + 1], w.maps[nxt[0]:nxt[0] + 1])
+            except _abi.IcarusError as e:
+                if e.code != _abi.ICR_ERR_STATE:
+                    raise
+                return
+            nxt[0] += 1
+            appends[0] += 1
+
+    chunk = 64
+    s.step(args.warmup)
+    feed()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    done = 0
+    while done < args.steps:
+        n = min(chunk, args.steps - done)
+        info = s.step(n)
+        assert info["steps"] == n and info["status"] == 0, info
+        done += n
+        feed()
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    t = s.clock()["t"]
+    log(f"bench: {args.steps} steps in {ms:.1f} ms, t = {t / 3600:.2f} h, {appends[0]} appends")
+    s.close()
+    out = {
+        "metric": "MHD cell-updates/s, extended domain with streamed maps", "unit": "cell-updates/s",
+        "value": g.cells * args.steps / (ms * 1e-3), "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms / args.steps, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": f"f{args.precision}", "data": "synthetic",
+        "config": {"workload": w.name, "cells": g.cells, "r_out_au": configs.JUPITER_AU,
+                   "map_cadence_s": float(w.times[1] - w.times[0]), "map_buffer": 4,
+                   "maps_appended_in_timed_region": appends[0], "simulated_h": t / 3600},
+        "roofline": None,
+    }
+    print(json.dumps(out), flush=True)
+
+
 def copy_calibration():
     """A plain device copy of 2 GiB, three times: the reference that scales
     the FETCH_SIZE / WRITE_SIZE counters to bytes."""
@@ -296,6 +364,9 @@ def main():
         return
     if args.workload == "relax":
         relax_bench(args)
+        return
+    if args.workload == "jupiter":
+        jupiter_bench(args)
         return
     import numpy as np
     import torch

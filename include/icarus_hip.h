@@ -163,6 +163,20 @@ int icr_grid_edges(const icr_solver *s, double *r_edges, double *th_edges,
 int icr_set_boundary_maps(icr_solver *s, int n_maps, const double *t_s,
                           const double *maps_si, int maps_on_device);
 
+/* Stream later maps into a run (long dynamic runs with more maps than fit,
+ * e.g. an extended domain with an hourly map cadence; Sect. 3 and 5).
+ * Appends n maps in the layout of icr_set_boundary_maps, with times strictly
+ * after the last map held.  First the maps that can no longer bracket any
+ * time from the clock on are dropped: those before the last map time <= t.
+ * The boundary values at times >= t are unchanged by the drop.  If the maps
+ * still needed plus the new ones exceed max_maps, nothing changes and
+ * ICR_ERR_STATE asks to step further first.  *n_held (may be NULL) receives
+ * the number of maps held afterwards.  Setting the clock back before the
+ * first map held later clamps to that map, as for any time before the first
+ * map. */
+int icr_append_boundary_maps(icr_solver *s, int n_maps, const double *t_s,
+                             const double *maps_si, int maps_on_device, int *n_held);
+
 /* Cone CMEs (Sect. 3.2 bc_icarus; Table 1 parameters): n <= max_cmes rows
  * of 8 SI values: insertion start [s], duration [s], latitude [rad],
  * co-rotating longitude [rad], half-width [rad], speed [m/s], density

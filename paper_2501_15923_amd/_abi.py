@@ -93,6 +93,7 @@ SIGNATURES = {
     "icr_ens_set_planes": (I, [P, I, I]),
     "icr_ens_set_mode": (I, [P, I, I, I]),
     "icr_ens_step": (I, [P, I, ctypes.c_double, ctypes.POINTER(IcrStepInfo)]),
+    "icr_append_boundary_maps": (I, [P, I, D, D, I, ctypes.POINTER(ctypes.c_int)]),
     "icr_set_tracer": (I, [P, D, I]),
     "icr_get_tracer": (I, [P, D, I]),
     "icr_divv": (I, [P, D, I]),

@@ -5,6 +5,8 @@ runs; see synth.py for how each input is drawn).
   prod_dynamic  600 x 60 x 120 cells, 10 maps 6 h apart, 3 simulated days,
                 4 probe trajectories
   prod_cme      prod_dynamic plus one cone CME (1000 km/s, 30 deg, 8 h)
+  jupiter_dynamic  outer boundary 5.5 AU (802 x 60 x 120), hourly maps to be
+                streamed into a small map buffer
 """
 from __future__ import annotations
 
@@ -54,3 +56,29 @@ def prod_cme(seed: int = 2, nr: int = 600, nt: int = 60, nph: int = 120) -> Work
     w.cmes = cme[None]
     w.probe_cadence = 600.0
     return w
+
+
+JUPITER_AU = 5.5
+
+
+def jupiter_dynamic(seed: int = 3, days: float = 2.0, cadence: float = HOUR, nt: int = 60,
+                    nph: int = 120) -> Workload:
+    """Domain extended to beyond Jupiter's orbit (outer boundary 5.5 AU), with
+    the radial stretching of the production grid (803 cells from 0.1 to
+    5.5 AU, the ratio of successive edges of 600 cells over 0.1-2 AU) and a
+    map every `cadence` seconds over `days`, meant to be streamed into a
+    small map buffer.  Probes: Venus-, Earth- and Mars-like circular orbits
+    (0.72, 1.0, 1.52 AU) and Jupiter's (5.2 AU)."""
+    import math
+    nr = int(round(600 * math.log(JUPITER_AU / 0.1) / math.log(20.0)))
+    g = Grid(nr, nt, nph, r_out=JUPITER_AU * synth.AU)
+    n_maps = int(round(days * DAY / cadence)) + 1
+    times, maps = synth.dynamic_maps(g, seed, n_maps=n_maps, cadence=cadence)
+    rng = np.random.default_rng(seed)
+    ph = rng.uniform(0.0, 2 * math.pi, 4)
+    t_end = days * DAY
+    probes = np.ascontiguousarray(np.stack([
+        synth.orbit_table(t_end, 600.0, a * synth.AU, 0.0, p)
+        for a, p in zip((0.72, 1.0, 1.52, 5.2), ph)]))
+    return Workload(f"jupiter_dynamic_{nr}x{nt}x{nph}", g, times, maps, np.zeros((0, 8)),
+                    probes, 0, t_end, probe_cadence=600.0)

@@ -171,6 +171,7 @@ struct icr_solver {
   int cur;                 // state buffer (0/1) holding the current state
   bool have_state, have_maps;
   int n_maps, n_cme, n_probes, n_pts;
+  std::vector<double> tau_h;  // map times (code units) held on the device, ascending
   double cadence;
   double r_in, omega, gm, dph;
   int tile_r, variant, use_graphs, planes;
@@ -503,16 +504,12 @@ int icr_grid_edges(const icr_solver* s, double* r, double* t, double* ph) {
   return ICR_OK;
 }
 
-int icr_set_boundary_maps(icr_solver* s, int n, const double* t_s, const double* maps,
-                          int on_device) {
-  if (!s) return fail(ICR_ERR_ARG, "solver is NULL");
-  if (n < 1 || n > s->g.max_maps)
-    return fail(ICR_ERR_ARG, "n_maps = %d outside [1, %d]", n, s->g.max_maps);
-  if (!t_s || !maps) return fail(ICR_ERR_ARG, "t_s and maps must not be NULL");
-  for (int q = 1; q < n; ++q)
-    if (!(t_s[q] > t_s[q - 1])) return fail(ICR_ERR_ARG, "map times must ascend strictly");
+namespace {
+// Copy n SI maps [n][8][nt][np] (host or device) into h in code units,
+// checking rho > 0, p > 0 and finiteness.
+int stage_maps(icr_solver* s, int n, const double* maps, int on_device, std::vector<double>& h) {
   const size_t plane = (size_t)s->g.n_theta * s->g.n_phi;
-  std::vector<double> h((size_t)n * NV * plane);
+  h.resize((size_t)n * NV * plane);
   if (on_device) {
     HIP_TRY(hipMemcpyAsync(h.data(), maps, h.size() * sizeof(double), hipMemcpyDeviceToHost,
                            s->stream));
@@ -530,6 +527,21 @@ int icr_set_boundary_maps(icr_solver* s, int n, const double* t_s, const double*
         if (!std::isfinite(x)) return fail(ICR_ERR_ARG, "map %d has a non-finite value", m);
         x /= sc.s[v];
       }
+  return ICR_OK;
+}
+}  // namespace
+
+int icr_set_boundary_maps(icr_solver* s, int n, const double* t_s, const double* maps,
+                          int on_device) {
+  if (!s) return fail(ICR_ERR_ARG, "solver is NULL");
+  if (n < 1 || n > s->g.max_maps)
+    return fail(ICR_ERR_ARG, "n_maps = %d outside [1, %d]", n, s->g.max_maps);
+  if (!t_s || !maps) return fail(ICR_ERR_ARG, "t_s and maps must not be NULL");
+  for (int q = 1; q < n; ++q)
+    if (!(t_s[q] > t_s[q - 1])) return fail(ICR_ERR_ARG, "map times must ascend strictly");
+  std::vector<double> h;
+  int rc = stage_maps(s, n, maps, on_device, h);
+  if (rc) return rc;
   std::vector<double> tau(n);
   for (int m = 0; m < n; ++m) tau[m] = t_s[m] / s->un.t;
   HIP_TRY(hipMemcpyAsync(s->ws + s->L.maps, h.data(), h.size() * sizeof(double),
@@ -537,9 +549,55 @@ int icr_set_boundary_maps(icr_solver* s, int n, const double* t_s, const double*
   HIP_TRY(hipMemcpyAsync(s->ws + s->L.tau, tau.data(), n * sizeof(double), hipMemcpyHostToDevice,
                          s->stream));
   HIP_TRY(hipStreamSynchronize(s->stream));
+  s->tau_h = tau;
   s->n_maps = n;
   s->have_maps = true;
   s->drop_graphs();
+  return ICR_OK;
+}
+
+int icr_append_boundary_maps(icr_solver* s, int n, const double* t_s, const double* maps,
+                             int on_device, int* n_held) {
+  if (!s) return fail(ICR_ERR_ARG, "solver is NULL");
+  if (!s->have_maps) return fail(ICR_ERR_STATE, "set the first maps with icr_set_boundary_maps");
+  if (n < 1) return fail(ICR_ERR_ARG, "n = %d < 1", n);
+  if (!t_s || !maps) return fail(ICR_ERR_ARG, "t_s and maps must not be NULL");
+  const double last = s->tau_h.back() * s->un.t;
+  for (int q = 0; q < n; ++q)
+    if (!(t_s[q] > (q ? t_s[q - 1] : last)))
+      return fail(ICR_ERR_ARG, "appended map times must ascend strictly after %.17g s", last);
+  // maps strictly before the last map time <= t can no longer bracket any
+  // time from the clock on
+  DevClock c;
+  int rc = s->read_clock(&c);
+  if (rc) return rc;
+  int keep = 0;
+  while (keep + 1 < s->n_maps && s->tau_h[keep + 1] <= c.t) ++keep;
+  const int held = s->n_maps - keep;
+  if (held + n > s->g.max_maps)
+    return fail(ICR_ERR_STATE,
+                "map buffer full: %d maps still bracket t >= %.6g s, %d more do not fit in "
+                "max_maps = %d (step further first)",
+                held, c.t * s->un.t, n, s->g.max_maps);
+  std::vector<double> h;
+  rc = stage_maps(s, n, maps, on_device, h);
+  if (rc) return rc;
+  const size_t mbytes = sizeof(double) * NV * (size_t)s->g.n_theta * s->g.n_phi;
+  char* base = s->ws + s->L.maps;
+  for (int q = 0; q < held && keep > 0; ++q)  // slot keep + q -> q (disjoint slots)
+    HIP_TRY(hipMemcpyAsync(base + q * mbytes, base + (size_t)(keep + q) * mbytes, mbytes,
+                           hipMemcpyDeviceToDevice, s->stream));
+  HIP_TRY(hipMemcpyAsync(base + (size_t)held * mbytes, h.data(), h.size() * sizeof(double),
+                         hipMemcpyHostToDevice, s->stream));
+  std::vector<double> tau(s->tau_h.begin() + keep, s->tau_h.end());
+  for (int q = 0; q < n; ++q) tau.push_back(t_s[q] / s->un.t);
+  HIP_TRY(hipMemcpyAsync(s->ws + s->L.tau, tau.data(), tau.size() * sizeof(double),
+                         hipMemcpyHostToDevice, s->stream));
+  HIP_TRY(hipStreamSynchronize(s->stream));
+  s->tau_h = tau;
+  s->n_maps = (int)tau.size();
+  s->drop_graphs();
+  if (n_held) *n_held = s->n_maps;
   return ICR_OK;
 }
 

@@ -103,6 +103,17 @@ class Solver:
         maps = np.ascontiguousarray(maps, dtype=np.float64)
         check(lib().icr_set_boundary_maps(self.h, len(times), _np_ptr(times), _np_ptr(maps), 0))
 
+    def append_maps(self, times, maps):
+        """Stream later maps in (older ones the clock has passed are dropped);
+        returns the number of maps held."""
+        times = np.ascontiguousarray(np.atleast_1d(times), dtype=np.float64)
+        maps = np.ascontiguousarray(maps, dtype=np.float64).reshape(
+            (len(times), 8, self.grid.nt, self.grid.np_))
+        held = ctypes.c_int()
+        check(lib().icr_append_boundary_maps(self.h, len(times), _np_ptr(times), _np_ptr(maps),
+                                             0, ctypes.byref(held)))
+        return held.value
+
     def set_cmes(self, rows):
         rows = np.ascontiguousarray(np.atleast_2d(rows), dtype=np.float64)
         n = 0 if rows.size == 0 else rows.shape[0]
