@@ -57,6 +57,8 @@ def parse():
                          "hourly maps streamed into a 4-map buffer")
     ap.add_argument("--runs", type=int, default=64)
     ap.add_argument("--maps", type=int, default=4, help="held-out maps for --workload relax")
+    ap.add_argument("--flux", default="tvdlf", choices=("tvdlf", "hll", "hlld"),
+                    help="face flux of the production run (the headline line uses tvdlf)")
     ap.add_argument("--tracer", action="store_true",
                     help="production grid with a cone CME and the passive CME tracer on")
     ap.add_argument("--ens-grid", default=None,
@@ -378,8 +380,9 @@ def main():
     g = w.grid
     log(f"bench: workload {w.name}, fp{args.precision}, steps {args.steps}, warmup {args.warmup}"
         + (", passive CME tracer on" if args.tracer else ""))
+    flux = {"tvdlf": 0, "hll": 1, "hlld": 2}[args.flux]
     s = Solver(g, precision=args.precision, probe_log_rows=args.steps + args.warmup + 16,
-               max_traj_pts=w.probes.shape[1], tracer=args.tracer)
+               max_traj_pts=w.probes.shape[1], tracer=args.tracer, flux=flux)
     s.set_launch(args.variant, 0, 0, 1)
     s.set_maps(w.times, w.maps)
     if len(w.cmes):
@@ -426,10 +429,12 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": f"f{args.precision}",
         "data": "synthetic",
         "config": {"workload": w.name, "cells": g.cells, "maps": len(w.times),
-                   "probes": int(w.probes.shape[0]), "flux": "TVDLF", "limiter": "minmod",
+                   "probes": int(w.probes.shape[0]), "flux": args.flux.upper(), "limiter": "minmod",
                    "rk": "SSP-RK2", "cfl": w.cfl, "parallelism": "single GPU"},
         "roofline": roof,
     }
+    if args.flux != "tvdlf":
+        out["roofline"]["traffic"] = None  # the counters were taken on the TVDLF kernel
     if args.tracer:
         # the stage intervals now include the tracer kernels: no stage roofline
         out["config"]["tracer"] = True

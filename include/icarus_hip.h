@@ -57,7 +57,10 @@ enum {
   ICR_ERR_UNSUPPORTED = -5   /* option not implemented                      */
 };
 
-enum { ICR_FLUX_TVDLF = 0, ICR_FLUX_HLL = 1 };
+/* Face fluxes: TVDLF (Rusanov), HLL, and HLLD (Miyoshi & Kusano 2005: the
+ * fast, rotational and contact waves; both face states use the mean normal
+ * field, whose own flux is the HLL value; single solvers only). */
+enum { ICR_FLUX_TVDLF = 0, ICR_FLUX_HLL = 1, ICR_FLUX_HLLD = 2 };
 enum { ICR_LIM_MINMOD = 0, ICR_LIM_MC = 1 };
 enum { ICR_PREC_F64 = 64, ICR_PREC_F32 = 32 };
 

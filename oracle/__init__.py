@@ -20,7 +20,7 @@ LIB_PATH = os.path.join(_HERE, "liborc_mhd.so")
 SRC_PATH = os.path.join(_HERE, "orc_mhd.c")
 
 GEOM_SPH, GEOM_SLAB = 0, 1
-FLUX_TVDLF, FLUX_HLL = 0, 1
+FLUX_TVDLF, FLUX_HLL, FLUX_HLLD = 0, 1, 2
 LIM_MINMOD, LIM_MC = 0, 1
 BCT_MAP, BCT_ASYMM = 0, 1
 BCM_DRIVEN, BCM_FROZEN = 0, 1
@@ -78,6 +78,7 @@ def lib():
         L.orc_tracer_flux.restype = ctypes.c_double
         L.orc_tracer_flux.argtypes = [P]
         L.orc_divv.argtypes = [P, D]
+        L.orc_face_flux.argtypes = [P, D, D, ctypes.c_int, D]
         _lib = L
     return _lib
 
@@ -231,6 +232,14 @@ class Oracle:
 
     def tracer_flux(self):
         return lib().orc_tracer_flux(self.h)
+
+    def face_flux(self, wl, wr, n):
+        """Numerical flux of primitive face states (code units), normal n = 1..3."""
+        wl = np.ascontiguousarray(wl, dtype=np.float64)
+        wr = np.ascontiguousarray(wr, dtype=np.float64)
+        out = np.zeros(8)
+        lib().orc_face_flux(self.h, _d(wl), _d(wr), int(n), _d(out))
+        return out
 
     def divv(self):
         out = np.zeros((self.np_, self.nt, self.nr))

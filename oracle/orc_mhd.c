@@ -52,7 +52,7 @@ static double u_pres(void) { return u_rho() * V_UNIT * V_UNIT; }
 static double u_bfield(void) { return sqrt(MU0_SI * u_rho()) * V_UNIT; }
 
 enum { GEOM_SPH = 0, GEOM_SLAB = 1 };
-enum { FLUX_TVDLF = 0, FLUX_HLL = 1 };
+enum { FLUX_TVDLF = 0, FLUX_HLL = 1, FLUX_HLLD = 2 };
 enum { LIM_MINMOD = 0, LIM_MC = 1 };
 enum { BCT_MAP = 0, BCT_ASYMM = 1 };
 enum { BCM_DRIVEN = 0, BCM_FROZEN = 1 };
@@ -176,9 +176,133 @@ static double limit(int lim, double a, double b) {
   return a > 0.0 ? m : -m;
 }
 
+/* HLLD flux (Miyoshi & Kusano 2005, J. Comput. Phys. 208, 315): the Riemann
+ * fan is split by the outer fast waves S_L, S_R, the rotational waves
+ * S*_L = S_M - |B_n|/sqrt(rho*_L), S*_R = S_M + |B_n|/sqrt(rho*_R) and the
+ * contact S_M into four intermediate states with continuous normal velocity
+ * (S_M) and total pressure (p_T*) across all of them, and density
+ * continuous across the rotational waves.  The two face states share one
+ * normal field, the mean of their B_n (a cell-centred scheme has a jump
+ * there); the flux of B_n itself is the HLL value with the same outer
+ * speeds, so its jump is still damped. */
+static void hlld_flux(double gam, const double *wl0, const double *wr0, int n,
+                      double *fs) {
+  int t1 = n == 1 ? 2 : 1, t2 = n == 3 ? 2 : 3; /* tangential components */
+  double bn = 0.5 * (wl0[4 + n] + wr0[4 + n]);
+  double wl[NV], wr[NV], ul[NV], ur[NV], fl[NV], fr[NV];
+  memcpy(wl, wl0, sizeof wl);
+  memcpy(wr, wr0, sizeof wr);
+  wl[4 + n] = bn;
+  wr[4 + n] = bn;
+  prim_to_cons(gam, wl, ul);
+  prim_to_cons(gam, wr, ur);
+  phys_flux(gam, wl, ul, n, fl);
+  phys_flux(gam, wr, ur, n, fr);
+  double cl = fast_speed(gam, wl, n), cr = fast_speed(gam, wr, n);
+  double cmax = cl > cr ? cl : cr;
+  double sl = (wl[n] < wr[n] ? wl[n] : wr[n]) - cmax;
+  double sr = (wl[n] > wr[n] ? wl[n] : wr[n]) + cmax;
+  /* HLL flux of the normal field (its physical flux is zero) */
+  double fbn = 0.0;
+  if (sl < 0.0 && sr > 0.0)
+    fbn = sl * sr * (wr0[4 + n] - wl0[4 + n]) / (sr - sl);
+  if (sl >= 0.0) {
+    memcpy(fs, fl, sizeof fl);
+    fs[4 + n] = fbn;
+    return;
+  }
+  if (sr <= 0.0) {
+    memcpy(fs, fr, sizeof fr);
+    fs[4 + n] = fbn;
+    return;
+  }
+  double ptl = wl[4] + 0.5 * (wl[5] * wl[5] + wl[6] * wl[6] + wl[7] * wl[7]);
+  double ptr = wr[4] + 0.5 * (wr[5] * wr[5] + wr[6] * wr[6] + wr[7] * wr[7]);
+  double dl = (sl - wl[n]) * wl[0], dr = (sr - wr[n]) * wr[0]; /* mass fluxes */
+  double sm = (dr * wr[n] - dl * wl[n] - ptr + ptl) / (dr - dl);
+  double pts = (dr * ptl - dl * ptr + dl * dr * (wr[n] - wl[n])) / (dr - dl);
+  /* outer star states: U*_a from the jump conditions across S_a */
+  double us[2][NV], rs[2];
+  for (int a = 0; a < 2; ++a) {
+    const double *w = a ? wr : wl, *u = a ? ur : ul;
+    double s = a ? sr : sl, d = a ? dr : dl, pt = a ? ptr : ptl;
+    double rho = d / (s - sm);
+    double den = d * (s - sm) - bn * bn;
+    double vt1, vt2, bt1, bt2;
+    if (fabs(den) <= 1e-12 * (fabs(d * (s - sm)) + bn * bn)) {
+      vt1 = w[t1]; vt2 = w[t2]; bt1 = w[4 + t1]; bt2 = w[4 + t2];
+    } else {
+      double fv = bn * (sm - w[n]) / den;
+      double fb = (d * (s - w[n]) - bn * bn) / den;
+      vt1 = w[t1] - w[4 + t1] * fv;
+      vt2 = w[t2] - w[4 + t2] * fv;
+      bt1 = w[4 + t1] * fb;
+      bt2 = w[4 + t2] * fb;
+    }
+    double vb = w[1] * w[5] + w[2] * w[6] + w[3] * w[7];
+    double vbs = sm * bn + vt1 * bt1 + vt2 * bt2;
+    double e = ((s - w[n]) * u[4] - pt * w[n] + pts * sm + bn * (vb - vbs)) / (s - sm);
+    double *q = us[a];
+    q[0] = rho;
+    q[n] = rho * sm;
+    q[t1] = rho * vt1;
+    q[t2] = rho * vt2;
+    q[4] = e;
+    q[4 + n] = bn;
+    q[4 + t1] = bt1;
+    q[4 + t2] = bt2;
+    rs[a] = sqrt(rho);
+  }
+  double sgn = bn >= 0.0 ? 1.0 : -1.0;
+  double ssl = sm - fabs(bn) / rs[0], ssr = sm + fabs(bn) / rs[1];
+  /* F*_a = F_a + S_a (U*_a - U_a) */
+  double fsl[NV], fsr[NV];
+  for (int v = 0; v < NV; ++v) {
+    fsl[v] = fl[v] + sl * (us[0][v] - ul[v]);
+    fsr[v] = fr[v] + sr * (us[1][v] - ur[v]);
+  }
+  if (ssl >= 0.0 || ssr <= 0.0) {
+    memcpy(fs, ssl >= 0.0 ? fsl : fsr, NV * sizeof(double));
+    fs[4 + n] = fbn;
+    return;
+  }
+  /* inner (double-star) states between the rotational waves */
+  double vl1 = us[0][t1] / us[0][0], vl2 = us[0][t2] / us[0][0];
+  double vr1 = us[1][t1] / us[1][0], vr2 = us[1][t2] / us[1][0];
+  double sq = rs[0] + rs[1];
+  double v1 = (rs[0] * vl1 + rs[1] * vr1 + (us[1][4 + t1] - us[0][4 + t1]) * sgn) / sq;
+  double v2 = (rs[0] * vl2 + rs[1] * vr2 + (us[1][4 + t2] - us[0][4 + t2]) * sgn) / sq;
+  double b1 = (rs[0] * us[1][4 + t1] + rs[1] * us[0][4 + t1] +
+               rs[0] * rs[1] * (vr1 - vl1) * sgn) / sq;
+  double b2 = (rs[0] * us[1][4 + t2] + rs[1] * us[0][4 + t2] +
+               rs[0] * rs[1] * (vr2 - vl2) * sgn) / sq;
+  double vbss = sm * bn + v1 * b1 + v2 * b2;
+  int a = sm >= 0.0 ? 0 : 1;
+  const double *q = us[a];
+  double vbs = (q[n] * q[4 + n] + q[t1] * q[4 + t1] + q[t2] * q[4 + t2]) / q[0];
+  double uss[NV];
+  uss[0] = q[0];
+  uss[n] = q[0] * sm;
+  uss[t1] = q[0] * v1;
+  uss[t2] = q[0] * v2;
+  uss[4] = q[4] + (a ? 1.0 : -1.0) * rs[a] * (vbs - vbss) * sgn;
+  uss[4 + n] = bn;
+  uss[4 + t1] = b1;
+  uss[4 + t2] = b2;
+  /* F**_a = F*_a + S*_a (U**_a - U*_a) */
+  double ssa = a ? ssr : ssl;
+  const double *fa = a ? fsr : fsl;
+  for (int v = 0; v < NV; ++v) fs[v] = fa[v] + ssa * (uss[v] - q[v]);
+  fs[4 + n] = fbn;
+}
+
 /* Numerical flux through one face from left/right face states. */
 static void face_flux(const orc_ctx *c, const double *wl, const double *wr,
                       int n, double *fs) {
+  if (c->flux == FLUX_HLLD) {
+    hlld_flux(c->gamma, wl, wr, n, fs);
+    return;
+  }
   double gam = c->gamma;
   double ul[NV], ur[NV], fl[NV], fr[NV];
   prim_to_cons(gam, wl, ul);
@@ -207,6 +331,12 @@ static void face_flux(const orc_ctx *c, const double *wl, const double *wr,
                 (sr - sl);
     }
   }
+}
+
+/* The numerical flux of this oracle's scheme for one face (test access):
+ * primitive face states wl, wr (code units), normal component n = 1..3. */
+void orc_face_flux(void *h, const double *wl, const double *wr, int n, double *out) {
+  face_flux((const orc_ctx *)h, wl, wr, n, out);
 }
 
 /* ---- grid ------------------------------------------------------------------ */

@@ -147,7 +147,7 @@ int validate(const icr_grid* g, const icr_phys* p) {
   if (!(p->gamma > 1.0)) return fail(ICR_ERR_ARG, "gamma must be > 1");
   if (!(p->cfl > 0.0 && p->cfl <= 1.0)) return fail(ICR_ERR_ARG, "cfl must be in (0, 1]");
   if (!std::isfinite(p->omega)) return fail(ICR_ERR_ARG, "omega must be finite");
-  if (p->flux != ICR_FLUX_TVDLF && p->flux != ICR_FLUX_HLL)
+  if (p->flux != ICR_FLUX_TVDLF && p->flux != ICR_FLUX_HLL && p->flux != ICR_FLUX_HLLD)
     return fail(ICR_ERR_ARG, "unknown flux %d", p->flux);
   if (p->limiter != ICR_LIM_MINMOD && p->limiter != ICR_LIM_MC)
     return fail(ICR_ERR_ARG, "unknown limiter %d", p->limiter);
@@ -1163,6 +1163,8 @@ int icr_ens_workspace_bytes(int n, const icr_grid* grids, const icr_phys* phys, 
   if (n < 1 || !grids || !bytes) return fail(ICR_ERR_ARG, "need n >= 1, grids and bytes");
   if (phys && phys->tracer)
     return fail(ICR_ERR_UNSUPPORTED, "the passive tracer is available for single solvers only");
+  if (phys && phys->flux == ICR_FLUX_HLLD)
+    return fail(ICR_ERR_UNSUPPORTED, "the HLLD flux is available for single solvers only");
   size_t total = ens_table_bytes(n);
   for (int r = 0; r < n; ++r) {
     int rc = validate(&grids[r], phys);

@@ -11,7 +11,7 @@ namespace icr {
 
 constexpr int NV = 8;  // rho, m_r, m_t, m_p, e, B_r, B_t, B_p
 
-enum : int { FLUX_TVDLF = 0, FLUX_HLL = 1 };
+enum : int { FLUX_TVDLF = 0, FLUX_HLL = 1, FLUX_HLLD = 2 };
 enum : int { LIM_MINMOD = 0, LIM_MC = 1 };
 
 constexpr int BAD_NONE = 0x7fffffff;
@@ -205,9 +205,133 @@ __device__ __forceinline__ void reconstruct(const R (&a)[NV], const R (&b)[NV],
 // Numerical flux from the two face states: TVDLF
 // F = (F_L + F_R)/2 - alpha (U_R - U_L)/2, alpha = max(|v_n| + c_f), or HLL
 // with S_L = min(v_nL - c_fL, v_nR - c_fR), S_R = max(v_nL + c_fL, ...).
+// HLLD flux (Miyoshi & Kusano 2005) through a face with normal component N:
+// the outer fast waves, the two rotational waves and the contact bound four
+// intermediate states sharing the contact speed S_M and total pressure;
+// density is continuous across the rotational waves.  Both face states use
+// the mean normal field; the normal field's own flux is the HLL value with
+// the same outer speeds.
+template <typename R, int N, bool FAST>
+__device__ __forceinline__ void hlld_flux(const R (&wl0)[NV], const R (&wr0)[NV], R gam, R igm1,
+                                          R (&fs)[NV]) {
+  constexpr int T1 = N == 1 ? 2 : 1, T2 = N == 3 ? 2 : 3;
+  auto rcp = [](R x) { return FAST ? rcp_fast(x) : R(1) / x; };
+  const R bn = R(0.5) * (wl0[4 + N] + wr0[4 + N]);
+  const R dbn = wr0[4 + N] - wl0[4 + N];
+  R w[2][NV], u[2][NV], f[2][NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    w[0][v] = wl0[v];
+    w[1][v] = wr0[v];
+  }
+  w[0][4 + N] = bn;
+  w[1][4 + N] = bn;
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    prim2cons<R>(w[a], u[a], igm1);
+    phys_flux<R, N>(w[a], u[a], f[a]);
+  }
+  const R cmax = rmax(cfast<R, N, FAST>(w[0], gam), cfast<R, N, FAST>(w[1], gam));
+  const R sl = rmin(w[0][N], w[1][N]) - cmax, sr = rmax(w[0][N], w[1][N]) + cmax;
+  const R fbn = (sl < R(0) && sr > R(0)) ? sl * sr * dbn * rcp(sr - sl) : R(0);
+  if (sl >= R(0) || sr <= R(0)) {
+    const bool left = sl >= R(0);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) fs[v] = left ? f[0][v] : f[1][v];
+    fs[4 + N] = fbn;
+    return;
+  }
+  R pt[2], d[2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    pt[a] = w[a][4] + R(0.5) * (w[a][5] * w[a][5] + w[a][6] * w[a][6] + w[a][7] * w[a][7]);
+    d[a] = ((a ? sr : sl) - w[a][N]) * w[a][0];  // mass flux relative to the outer wave
+  }
+  const R idd = rcp(d[1] - d[0]);
+  const R sm = (d[1] * w[1][N] - d[0] * w[0][N] - pt[1] + pt[0]) * idd;
+  const R pts = (d[1] * pt[0] - d[0] * pt[1] + d[0] * d[1] * (w[1][N] - w[0][N])) * idd;
+  // outer star states and their fluxes F*_a = F_a + S_a (U*_a - U_a)
+  R us[2][NV], sq[2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+    const R s = a ? sr : sl;
+    const R ism = rcp(s - sm);
+    const R rho = d[a] * ism;
+    const R den = d[a] * (s - sm) - bn * bn;
+    R vt1 = w[a][T1], vt2 = w[a][T2], bt1 = w[a][4 + T1], bt2 = w[a][4 + T2];
+    if (fabs(den) > R(1e-12) * (fabs(d[a] * (s - sm)) + bn * bn)) {
+      const R iden = rcp(den);
+      const R fv = bn * (sm - w[a][N]) * iden;
+      const R fb = (d[a] * (s - w[a][N]) - bn * bn) * iden;
+      vt1 -= bt1 * fv;
+      vt2 -= bt2 * fv;
+      bt1 *= fb;
+      bt2 *= fb;
+    }
+    const R vb = w[a][1] * w[a][5] + w[a][2] * w[a][6] + w[a][3] * w[a][7];
+    const R vbs = sm * bn + vt1 * bt1 + vt2 * bt2;
+    us[a][0] = rho;
+    us[a][N] = rho * sm;
+    us[a][T1] = rho * vt1;
+    us[a][T2] = rho * vt2;
+    us[a][4] = ((s - w[a][N]) * u[a][4] - pt[a] * w[a][N] + pts * sm + bn * (vb - vbs)) * ism;
+    us[a][4 + N] = bn;
+    us[a][4 + T1] = bt1;
+    us[a][4 + T2] = bt2;
+    sq[a] = FAST ? sqrt_fast(rho) : sqrt(rho);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) f[a][v] += s * (us[a][v] - u[a][v]);
+  }
+  const R ssl = sm - fabs(bn) * rcp(sq[0]), ssr = sm + fabs(bn) * rcp(sq[1]);
+  if (ssl >= R(0) || ssr <= R(0)) {
+    const bool left = ssl >= R(0);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) fs[v] = left ? f[0][v] : f[1][v];
+    fs[4 + N] = fbn;
+    return;
+  }
+  // double-star state on the side of the contact the face lies on
+  const R sg = bn >= R(0) ? R(1) : R(-1);
+  const R isq = rcp(sq[0] + sq[1]);
+  const R vl1 = us[0][T1] / us[0][0], vl2 = us[0][T2] / us[0][0];
+  const R vr1 = us[1][T1] / us[1][0], vr2 = us[1][T2] / us[1][0];
+  const R v1 = (sq[0] * vl1 + sq[1] * vr1 + (us[1][4 + T1] - us[0][4 + T1]) * sg) * isq;
+  const R v2 = (sq[0] * vl2 + sq[1] * vr2 + (us[1][4 + T2] - us[0][4 + T2]) * sg) * isq;
+  const R b1 = (sq[0] * us[1][4 + T1] + sq[1] * us[0][4 + T1] + sq[0] * sq[1] * (vr1 - vl1) * sg) *
+               isq;
+  const R b2 = (sq[0] * us[1][4 + T2] + sq[1] * us[0][4 + T2] + sq[0] * sq[1] * (vr2 - vl2) * sg) *
+               isq;
+  const bool left = sm >= R(0);
+  R q[NV], fa[NV];
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    q[v] = left ? us[0][v] : us[1][v];
+    fa[v] = left ? f[0][v] : f[1][v];
+  }
+  const R vbs = (q[N] * q[4 + N] + q[T1] * q[4 + T1] + q[T2] * q[4 + T2]) / q[0];
+  const R vbss = sm * bn + v1 * b1 + v2 * b2;
+  R uss[NV];
+  uss[0] = q[0];
+  uss[N] = q[0] * sm;
+  uss[T1] = q[0] * v1;
+  uss[T2] = q[0] * v2;
+  uss[4] = q[4] + (left ? -sq[0] : sq[1]) * (vbs - vbss) * sg;
+  uss[4 + N] = bn;
+  uss[4 + T1] = b1;
+  uss[4 + T2] = b2;
+  const R ssa = left ? ssl : ssr;
+#pragma unroll
+  for (int v = 0; v < NV; ++v) fs[v] = fa[v] + ssa * (uss[v] - q[v]);
+  fs[4 + N] = fbn;
+}
+
 template <typename R, int N, int FLUX, bool FAST = false>
 __device__ __forceinline__ void face_flux(const R (&wl)[NV], const R (&wr)[NV],
                                           R gam, R igm1, R (&fs)[NV]) {
+  if constexpr (FLUX == FLUX_HLLD) {
+    hlld_flux<R, N, FAST>(wl, wr, gam, igm1, fs);
+    return;
+  }
   R ul[NV], ur[NV], fl[NV], fr[NV];
   prim2cons<R>(wl, ul, igm1);
   prim2cons<R>(wr, ur, igm1);

@@ -320,6 +320,9 @@ void launch_stage(const StageArgs<R>& a, int stage, int flux, int lim, dim3 grid
   if (flux == FLUX_TVDLF) {
     if (lim == LIM_MINMOD) launch_stage_t<R, FLUX_TVDLF, LIM_MINMOD>(a, stage, grid, blk, s);
     else launch_stage_t<R, FLUX_TVDLF, LIM_MC>(a, stage, grid, blk, s);
+  } else if (flux == FLUX_HLLD) {
+    if (lim == LIM_MINMOD) launch_stage_t<R, FLUX_HLLD, LIM_MINMOD>(a, stage, grid, blk, s);
+    else launch_stage_t<R, FLUX_HLLD, LIM_MC>(a, stage, grid, blk, s);
   } else {
     if (lim == LIM_MINMOD) launch_stage_t<R, FLUX_HLL, LIM_MINMOD>(a, stage, grid, blk, s);
     else launch_stage_t<R, FLUX_HLL, LIM_MC>(a, stage, grid, blk, s);

@@ -38,6 +38,11 @@ static void launch_lds_tile(const StageArgs<R>& a, int stage, int flux, int lim,
       launch_lds_t<R, TR, TT, FLUX_TVDLF, LIM_MINMOD, FM>(a, stage, kplanes, s);
     else
       launch_lds_t<R, TR, TT, FLUX_TVDLF, LIM_MC, FM>(a, stage, kplanes, s);
+  } else if (flux == FLUX_HLLD) {
+    if (lim == LIM_MINMOD)
+      launch_lds_t<R, TR, TT, FLUX_HLLD, LIM_MINMOD, FM>(a, stage, kplanes, s);
+    else
+      launch_lds_t<R, TR, TT, FLUX_HLLD, LIM_MC, FM>(a, stage, kplanes, s);
   } else {
     if (lim == LIM_MINMOD)
       launch_lds_t<R, TR, TT, FLUX_HLL, LIM_MINMOD, FM>(a, stage, kplanes, s);
