@@ -21,7 +21,7 @@ SRC_PATH = os.path.join(_HERE, "orc_mhd.c")
 
 GEOM_SPH, GEOM_SLAB = 0, 1
 FLUX_TVDLF, FLUX_HLL, FLUX_HLLD = 0, 1, 2
-LIM_MINMOD, LIM_MC = 0, 1
+LIM_MINMOD, LIM_MC, LIM_WENO5 = 0, 1, 2
 BCT_MAP, BCT_ASYMM = 0, 1
 BCM_DRIVEN, BCM_FROZEN = 0, 1
 SLABX_OUTFLOW, SLABX_PERIODIC = 0, 1
@@ -79,6 +79,7 @@ def lib():
         L.orc_tracer_flux.argtypes = [P]
         L.orc_divv.argtypes = [P, D]
         L.orc_face_flux.argtypes = [P, D, D, ctypes.c_int, D]
+        L.orc_ghosts.argtypes = [P]
         _lib = L
     return _lib
 
@@ -132,7 +133,8 @@ class Oracle:
 
     @property
     def padded_shape(self):
-        return (8, self.np_ + 4, self.nt + 4, self.nr + 4)
+        g = 2 * lib().orc_ghosts(self.h)
+        return (8, self.np_ + g, self.nt + g, self.nr + g)
 
     def edges(self):
         r = np.zeros(self.nr + 1)

@@ -35,7 +35,8 @@
 #include <string.h>
 
 #define NV 8 /* rho, m_r, m_t, m_p, e, B_r, B_t, B_p (or rho, v.., p, B..) */
-#define NG 2 /* ghost layers on each side */
+/* ghost layers on each side: 2 for the slope-limited reconstructions, 3
+ * for WENO5 (c->ng) */
 
 /* ---- units: code = SI / unit --------------------------------------------- */
 static const double AU_M = 1.495978707e11;      /* length unit [m]       */
@@ -53,14 +54,15 @@ static double u_bfield(void) { return sqrt(MU0_SI * u_rho()) * V_UNIT; }
 
 enum { GEOM_SPH = 0, GEOM_SLAB = 1 };
 enum { FLUX_TVDLF = 0, FLUX_HLL = 1, FLUX_HLLD = 2 };
-enum { LIM_MINMOD = 0, LIM_MC = 1 };
+enum { LIM_MINMOD = 0, LIM_MC = 1, LIM_WENO5 = 2 };
 enum { BCT_MAP = 0, BCT_ASYMM = 1 };
 enum { BCM_DRIVEN = 0, BCM_FROZEN = 1 };
 enum { SLABX_OUTFLOW = 0, SLABX_PERIODIC = 1 };
 
 typedef struct {
   int nr, nt, np;  /* active cells along r(x), theta(y), phi(z) */
-  int gr, gt, gp;  /* padded sizes n + 2*NG */
+  int ng;          /* ghost layers on each side */
+  int gr, gt, gp;  /* padded sizes n + 2*ng */
   int geom, flux, limiter, gravity, corot, bc_transverse, bc_mode, slab_bcx;
   double gamma, omega, gm, cfl; /* code units */
   /* edges of the active cells (n+1 each), code units / radians */
@@ -97,7 +99,7 @@ static size_t pad_cells(const orc_ctx *c) {
 }
 /* index into a padded array; i, j, k are active-cell indices (may be <0). */
 static size_t IX(const orc_ctx *c, int v, int i, int j, int k) {
-  return (((size_t)v * c->gp + (k + NG)) * c->gt + (j + NG)) * c->gr + (i + NG);
+  return (((size_t)v * c->gp + (k + c->ng)) * c->gt + (j + c->ng)) * c->gr + (i + c->ng);
 }
 
 /* ---- state conversions: Eq. (6) with mu0 = 1 ----------------------------- */
@@ -162,6 +164,30 @@ static void phys_flux(double gam, const double *w, const double *u, int n,
   }
   f[4] = (u[4] + ptot) * vn - bn * vb;
   for (int d = 1; d <= 3; ++d) f[4 + d] = vn * w[4 + d] - bn * w[d];
+}
+
+/* WENO5 (Jiang & Shu 1996) value at the face between cells c and d from
+ * the five cells a..e: the three third-order candidates of the stencils
+ * ending at c, centred on c and starting at c, blended with weights
+ * d_k / (eps + beta_k)^2 (d = 1/10, 6/10, 3/10) where beta_k measures each
+ * candidate's smoothness.  eps is relative to the stencil's magnitude
+ * (1e-6 of the mean square, plus 1e-40), so the weights do not depend on
+ * the units of the variable. */
+static double weno5(double a, double b, double c, double d, double e) {
+  double q0 = (2.0 * a - 7.0 * b + 11.0 * c) / 6.0;
+  double q1 = (-b + 5.0 * c + 2.0 * d) / 6.0;
+  double q2 = (2.0 * c + 5.0 * d - e) / 6.0;
+  double b0 = 13.0 / 12.0 * (a - 2.0 * b + c) * (a - 2.0 * b + c) +
+              0.25 * (a - 4.0 * b + 3.0 * c) * (a - 4.0 * b + 3.0 * c);
+  double b1 = 13.0 / 12.0 * (b - 2.0 * c + d) * (b - 2.0 * c + d) +
+              0.25 * (b - d) * (b - d);
+  double b2 = 13.0 / 12.0 * (c - 2.0 * d + e) * (c - 2.0 * d + e) +
+              0.25 * (3.0 * c - 4.0 * d + e) * (3.0 * c - 4.0 * d + e);
+  double eps = 1e-6 * (a * a + b * b + c * c + d * d + e * e) / 5.0 + 1e-40;
+  double a0 = 0.1 / ((eps + b0) * (eps + b0));
+  double a1 = 0.6 / ((eps + b1) * (eps + b1));
+  double a2 = 0.3 / ((eps + b2) * (eps + b2));
+  return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
 }
 
 /* Slope limiters on undivided differences a = W_i - W_{i-1},
@@ -335,6 +361,8 @@ static void face_flux(const orc_ctx *c, const double *wl, const double *wr,
 
 /* The numerical flux of this oracle's scheme for one face (test access):
  * primitive face states wl, wr (code units), normal component n = 1..3. */
+int orc_ghosts(const void *h) { return ((const orc_ctx *)h)->ng; }
+
 void orc_face_flux(void *h, const double *wl, const double *wr, int n, double *out) {
   face_flux((const orc_ctx *)h, wl, wr, n, out);
 }
@@ -427,9 +455,10 @@ void *orc_create(const int *ip, const double *dp) {
   c->bc_mode = ip[9];
   c->slab_bcx = ip[10];
   c->tracer = ip[11] && ip[3] == GEOM_SPH;
-  c->gr = c->nr + 2 * NG;
-  c->gt = c->nt + 2 * NG;
-  c->gp = c->np + 2 * NG;
+  c->ng = c->limiter == LIM_WENO5 ? 3 : 2;
+  c->gr = c->nr + 2 * c->ng;
+  c->gt = c->nt + 2 * c->ng;
+  c->gp = c->np + 2 * c->ng;
   c->gamma = dp[4];
   c->cfl = dp[6];
   if (c->geom == GEOM_SPH) {
@@ -619,7 +648,7 @@ static void fill_ghosts(orc_ctx *c, double *U, double t) {
       for (int j = 0; j < nt; ++j) {
         double w[NV], u[NV];
         inner_boundary_prim(c, t, j, k, w);
-        for (int g = 1; g <= NG; ++g) {
+        for (int g = 1; g <= c->ng; ++g) {
           double wg[NV];
           memcpy(wg, w, sizeof wg);
           if (c->bc_transverse == BCT_ASYMM) {
@@ -641,7 +670,7 @@ static void fill_ghosts(orc_ctx *c, double *U, double t) {
     for (int v = 0; v < NV; ++v)
       for (int k = 0; k < np; ++k)
         for (int j = 0; j < nt; ++j)
-          for (int g = 0; g < NG; ++g)
+          for (int g = 0; g < c->ng; ++g)
             U[IX(c, v, nr + g, j, k)] = U[IX(c, v, nr - 1, j, k)];
     /* colatitude edges: reflecting.  Ghost layer g mirrors active row g-1
      * from the edge (the last row when the grid has fewer rows) with the
@@ -651,7 +680,7 @@ static void fill_ghosts(orc_ctx *c, double *U, double t) {
       double sgn = (v == 2 || v == 6) ? -1.0 : 1.0;
       for (int k = 0; k < np; ++k)
         for (int i = 0; i < nr; ++i)
-          for (int g = 1; g <= NG; ++g) {
+          for (int g = 1; g <= c->ng; ++g) {
             int lo = g - 1 < nt ? g - 1 : nt - 1;
             int hi = nt - g >= 0 ? nt - g : 0;
             U[IX(c, v, i, -g, k)] = sgn * U[IX(c, v, i, lo, k)];
@@ -662,7 +691,7 @@ static void fill_ghosts(orc_ctx *c, double *U, double t) {
     for (int v = 0; v < NV; ++v)
       for (int k = 0; k < np; ++k)
         for (int j = 0; j < nt; ++j)
-          for (int g = 1; g <= NG; ++g) {
+          for (int g = 1; g <= c->ng; ++g) {
             if (c->slab_bcx == SLABX_PERIODIC) {
               U[IX(c, v, -g, j, k)] = U[IX(c, v, nr - g, j, k)];
               U[IX(c, v, nr - 1 + g, j, k)] = U[IX(c, v, g - 1, j, k)];
@@ -674,16 +703,16 @@ static void fill_ghosts(orc_ctx *c, double *U, double t) {
     for (int v = 0; v < NV; ++v)
       for (int k = 0; k < np; ++k)
         for (int i = 0; i < nr; ++i)
-          for (int g = 1; g <= NG; ++g) {
+          for (int g = 1; g <= c->ng; ++g) {
             U[IX(c, v, i, -g, k)] = U[IX(c, v, i, nt - g, k)];
             U[IX(c, v, i, nt - 1 + g, k)] = U[IX(c, v, i, g - 1, k)];
           }
   }
   /* longitude: periodic (slab z: periodic) */
   for (int v = 0; v < NV; ++v)
-    for (int g = 1; g <= NG; ++g)
-      for (int j = -NG; j < nt + NG; ++j)
-        for (int i = -NG; i < nr + NG; ++i) {
+    for (int g = 1; g <= c->ng; ++g)
+      for (int j = -c->ng; j < nt + c->ng; ++j)
+        for (int i = -c->ng; i < nr + c->ng; ++i) {
           U[IX(c, v, i, j, -g)] = U[IX(c, v, i, j, np - g)];
           U[IX(c, v, i, j, np - 1 + g)] = U[IX(c, v, i, j, g - 1)];
         }
@@ -711,20 +740,20 @@ static void tracer_upwind(orc_ctx *c, const double *U, const double *T, double t
       double ind = 0.0;
       for (int q = 0; q < c->n_cme; ++q)
         if (in_cme(c, t, j, k, q)) ind = 1.0;
-      for (int g = 1; g <= NG; ++g) {
+      for (int g = 1; g <= c->ng; ++g) {
         c->P[IX(c, 0, -g, j, k)] = ind;
         c->P[IX(c, 0, nr - 1 + g, j, k)] = c->P[IX(c, 0, nr - 1, j, k)];
       }
     }
   for (int k = 0; k < np; ++k)
     for (int i = 0; i < nr; ++i)
-      for (int g = 1; g <= NG; ++g) {
+      for (int g = 1; g <= c->ng; ++g) {
         c->P[IX(c, 0, i, -g, k)] = c->P[IX(c, 0, i, 0, k)];
         c->P[IX(c, 0, i, nt - 1 + g, k)] = c->P[IX(c, 0, i, nt - 1, k)];
       }
   for (int j = 0; j < nt; ++j)
     for (int i = 0; i < nr; ++i)
-      for (int g = 1; g <= NG; ++g) {
+      for (int g = 1; g <= c->ng; ++g) {
         c->P[IX(c, 0, i, j, -g)] = c->P[IX(c, 0, i, j, np - g)];
         c->P[IX(c, 0, i, j, np - 1 + g)] = c->P[IX(c, 0, i, j, g - 1)];
       }
@@ -776,11 +805,27 @@ static void compute_rhs(orc_ctx *c, double *U, double *L, double *bnd,
             w0[v] = W[IX(c, v, i, j, k)];
             wp1[v] = W[IX(c, v, i + di, j + dj, k + dk)];
           }
-          for (int v = 0; v < NV; ++v) {
-            double sl = limit(c->limiter, wm1[v] - wm2[v], w0[v] - wm1[v]);
-            double sr = limit(c->limiter, w0[v] - wm1[v], wp1[v] - w0[v]);
-            wl[v] = wm1[v] + 0.5 * sl;
-            wr[v] = w0[v] - 0.5 * sr;
+          if (c->limiter == LIM_WENO5) {
+            /* face m-1/2 from cells m-3 .. m+2; a face state with rho or p
+             * <= 0 falls back to its cell value (first order) */
+            double wm3[NV], wp2[NV];
+            for (int v = 0; v < NV; ++v) {
+              wm3[v] = W[IX(c, v, i - 3 * di, j - 3 * dj, k - 3 * dk)];
+              wp2[v] = W[IX(c, v, i + 2 * di, j + 2 * dj, k + 2 * dk)];
+            }
+            for (int v = 0; v < NV; ++v) {
+              wl[v] = weno5(wm3[v], wm2[v], wm1[v], w0[v], wp1[v]);
+              wr[v] = weno5(wp2[v], wp1[v], w0[v], wm1[v], wm2[v]);
+            }
+            if (!(wl[0] > 0.0 && wl[4] > 0.0)) memcpy(wl, wm1, sizeof wl);
+            if (!(wr[0] > 0.0 && wr[4] > 0.0)) memcpy(wr, w0, sizeof wr);
+          } else {
+            for (int v = 0; v < NV; ++v) {
+              double sl = limit(c->limiter, wm1[v] - wm2[v], w0[v] - wm1[v]);
+              double sr = limit(c->limiter, w0[v] - wm1[v], wp1[v] - w0[v]);
+              wl[v] = wm1[v] + 0.5 * sl;
+              wr[v] = w0[v] - 0.5 * sr;
+            }
           }
           face_flux(c, wl, wr, dir + 1, fs);
           for (int v = 0; v < NV; ++v) F[IX(c, v, i, j, k)] = fs[v];
