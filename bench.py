@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--maps", type=int, default=4, help="held-out maps for --workload relax")
     ap.add_argument("--flux", default="tvdlf", choices=("tvdlf", "hll", "hlld"),
                     help="face flux of the production run (the headline line uses tvdlf)")
+    ap.add_argument("--limiter", default="minmod", choices=("minmod", "mc", "weno5"),
+                    help="reconstruction of the production run (the headline line uses minmod)")
     ap.add_argument("--tracer", action="store_true",
                     help="production grid with a cone CME and the passive CME tracer on")
     ap.add_argument("--ens-grid", default=None,
@@ -381,8 +383,9 @@ def main():
     log(f"bench: workload {w.name}, fp{args.precision}, steps {args.steps}, warmup {args.warmup}"
         + (", passive CME tracer on" if args.tracer else ""))
     flux = {"tvdlf": 0, "hll": 1, "hlld": 2}[args.flux]
+    lim = {"minmod": 0, "mc": 1, "weno5": 2}[args.limiter]
     s = Solver(g, precision=args.precision, probe_log_rows=args.steps + args.warmup + 16,
-               max_traj_pts=w.probes.shape[1], tracer=args.tracer, flux=flux)
+               max_traj_pts=w.probes.shape[1], tracer=args.tracer, flux=flux, limiter=lim)
     s.set_launch(args.variant, 0, 0, 1)
     s.set_maps(w.times, w.maps)
     if len(w.cmes):
@@ -429,12 +432,12 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": f"f{args.precision}",
         "data": "synthetic",
         "config": {"workload": w.name, "cells": g.cells, "maps": len(w.times),
-                   "probes": int(w.probes.shape[0]), "flux": args.flux.upper(), "limiter": "minmod",
+                   "probes": int(w.probes.shape[0]), "flux": args.flux.upper(), "limiter": args.limiter,
                    "rk": "SSP-RK2", "cfl": w.cfl, "parallelism": "single GPU"},
         "roofline": roof,
     }
-    if args.flux != "tvdlf":
-        out["roofline"]["traffic"] = None  # the counters were taken on the TVDLF kernel
+    if args.flux != "tvdlf" or args.limiter != "minmod":
+        out["roofline"]["traffic"] = None  # the counters were taken on the TVDLF/minmod kernel
     if args.tracer:
         # the stage intervals now include the tracer kernels: no stage roofline
         out["config"]["tracer"] = True

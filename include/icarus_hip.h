@@ -61,7 +61,11 @@ enum {
  * fast, rotational and contact waves; both face states use the mean normal
  * field, whose own flux is the HLL value; single solvers only). */
 enum { ICR_FLUX_TVDLF = 0, ICR_FLUX_HLL = 1, ICR_FLUX_HLLD = 2 };
-enum { ICR_LIM_MINMOD = 0, ICR_LIM_MC = 1 };
+/* Reconstruction on primitives: minmod or MC limited slopes (two ghost
+ * layers), or WENO5 (Jiang & Shu 1996; three ghost layers, the
+ * thread-per-cell stage kernel only, single solvers only; a face state with
+ * rho or p <= 0 falls back to its cell value). */
+enum { ICR_LIM_MINMOD = 0, ICR_LIM_MC = 1, ICR_LIM_WENO5 = 2 };
 enum { ICR_PREC_F64 = 64, ICR_PREC_F32 = 32 };
 
 /* State kinds for icr_set_state / icr_get_state. */
@@ -273,7 +277,8 @@ int icr_boundary_at(icr_solver *s, double t_s, double *out);
  * (2), 1 = one thread per cell with on-the-fly neighbour primitives, 2 =
  * face-once kernel (LDS tile with halo in r/theta, registers along phi).
  * tile_r: lanes along r per block (variant 1: 64, 128, 256; variant 2: 32,
- * 64; 0 = 64; a solver with the passive tracer keeps 64 for variant 2);
+ * 64; 0 = 64; a solver with the passive tracer keeps 64 for variant 2; a
+ * WENO5 solver always runs variant 1);
  * 256 threads per block.  planes: phi planes per block of
  * variant 2 (1..n_phi, 0 = 8).  use_graphs: 1 replays steps from captured
  * HIP graphs.  All tiles and plane counts of one variant give bit-identical

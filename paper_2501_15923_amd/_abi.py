@@ -10,7 +10,7 @@ LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libicarus_h
 ICR_OK, ICR_ERR_ARG, ICR_ERR_STATE, ICR_ERR_NONPHYSICAL, ICR_ERR_HIP, ICR_ERR_UNSUPPORTED = \
     0, -1, -2, -3, -4, -5
 FLUX_TVDLF, FLUX_HLL, FLUX_HLLD = 0, 1, 2
-LIM_MINMOD, LIM_MC = 0, 1
+LIM_MINMOD, LIM_MC, LIM_WENO5 = 0, 1, 2
 PREC_F64, PREC_F32 = 64, 32
 STATE_PRIM_SI, STATE_CONS_CODE = 0, 1
 

@@ -149,7 +149,7 @@ int validate(const icr_grid* g, const icr_phys* p) {
   if (!std::isfinite(p->omega)) return fail(ICR_ERR_ARG, "omega must be finite");
   if (p->flux != ICR_FLUX_TVDLF && p->flux != ICR_FLUX_HLL && p->flux != ICR_FLUX_HLLD)
     return fail(ICR_ERR_ARG, "unknown flux %d", p->flux);
-  if (p->limiter != ICR_LIM_MINMOD && p->limiter != ICR_LIM_MC)
+  if (p->limiter != ICR_LIM_MINMOD && p->limiter != ICR_LIM_MC && p->limiter != ICR_LIM_WENO5)
     return fail(ICR_ERR_ARG, "unknown limiter %d", p->limiter);
   if (p->precision != ICR_PREC_F64 && p->precision != ICR_PREC_F32)
     return fail(ICR_ERR_ARG, "precision must be 64 or 32");
@@ -436,7 +436,7 @@ int icr_create(const icr_grid* g, const icr_phys* p, void* ws, size_t ws_bytes, 
   s->gm = p->gravity ? kGM / (s->un.len * s->un.v * s->un.v) : 0.0;
   s->dph = 2.0 * kPi / g->n_phi;
   s->tile_r = 64;
-  s->variant = 2;
+  s->variant = p->limiter == ICR_LIM_WENO5 ? 1 : 2;  // WENO5: thread-per-cell kernel only
   s->planes = 8;
   s->use_graphs = 1;
   s->graphs_ok = false;
@@ -1023,6 +1023,10 @@ int icr_profile_steps(icr_solver* s, int n, double* avg_ms) {
 int icr_set_launch(icr_solver* s, int variant, int tile_r, int planes, int use_graphs) {
   if (!s) return fail(ICR_ERR_ARG, "solver is NULL");
   if (variant == 0) variant = 2;
+  if (s->p.limiter == ICR_LIM_WENO5) {  // the face-once kernel has a 2-cell halo
+    variant = 1;
+    if (tile_r != 64 && tile_r != 128 && tile_r != 256) tile_r = 64;
+  }
   if (variant != 1 && variant != 2) return fail(ICR_ERR_ARG, "variant must be 0, 1 or 2");
   if (tile_r == 0) tile_r = 64;
   if (variant == 1 && tile_r != 64 && tile_r != 128 && tile_r != 256)
@@ -1165,6 +1169,8 @@ int icr_ens_workspace_bytes(int n, const icr_grid* grids, const icr_phys* phys, 
     return fail(ICR_ERR_UNSUPPORTED, "the passive tracer is available for single solvers only");
   if (phys && phys->flux == ICR_FLUX_HLLD)
     return fail(ICR_ERR_UNSUPPORTED, "the HLLD flux is available for single solvers only");
+  if (phys && phys->limiter == ICR_LIM_WENO5)
+    return fail(ICR_ERR_UNSUPPORTED, "WENO5 is available for single solvers only");
   size_t total = ens_table_bytes(n);
   for (int r = 0; r < n; ++r) {
     int rc = validate(&grids[r], phys);

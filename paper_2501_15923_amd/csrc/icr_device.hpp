@@ -12,7 +12,7 @@ namespace icr {
 constexpr int NV = 8;  // rho, m_r, m_t, m_p, e, B_r, B_t, B_p
 
 enum : int { FLUX_TVDLF = 0, FLUX_HLL = 1, FLUX_HLLD = 2 };
-enum : int { LIM_MINMOD = 0, LIM_MC = 1 };
+enum : int { LIM_MINMOD = 0, LIM_MC = 1, LIM_WENO5 = 2 };  // WENO5: 3 ghost layers
 
 constexpr int BAD_NONE = 0x7fffffff;
 
@@ -200,6 +200,58 @@ __device__ __forceinline__ void reconstruct(const R (&a)[NV], const R (&b)[NV],
     wl[v] = b[v] + R(0.5) * limiter<R, LIM, FAST>(db, dc);
     wr[v] = c[v] - R(0.5) * limiter<R, LIM, FAST>(dc, dd);
   }
+}
+
+// WENO5 (Jiang & Shu 1996) value at the face between cells c and d from the
+// five cells a..e: the three third-order candidates of the stencils ending
+// at, centred on and starting at c, weighted by d_k / (eps + beta_k)^2 with
+// linear weights (1, 6, 3)/10 and smoothness indicators beta_k; eps is 1e-6
+// of the stencil's mean square (plus 1e-40), so the weights are free of units.
+template <typename R>
+__device__ __forceinline__ R weno5(R a, R b, R c, R d, R e) {
+  constexpr R sixth = R(1) / R(6);
+  const R q0 = (R(2) * a - R(7) * b + R(11) * c) * sixth;
+  const R q1 = (-b + R(5) * c + R(2) * d) * sixth;
+  const R q2 = (R(2) * c + R(5) * d - e) * sixth;
+  const R s0 = a - R(2) * b + c, t0 = a - R(4) * b + R(3) * c;
+  const R s1 = b - R(2) * c + d, t1 = b - d;
+  const R s2 = c - R(2) * d + e, t2 = R(3) * c - R(4) * d + e;
+  const R b0 = R(13) / R(12) * s0 * s0 + R(0.25) * t0 * t0;
+  const R b1 = R(13) / R(12) * s1 * s1 + R(0.25) * t1 * t1;
+  const R b2 = R(13) / R(12) * s2 * s2 + R(0.25) * t2 * t2;
+  // absolute floor: (floor)^2 must stay a normal number (FP32: 1e-15)
+  const R eps = R(1e-6) * (a * a + b * b + c * c + d * d + e * e) * R(0.2) +
+                (sizeof(R) == 8 ? R(1e-40) : R(1e-15));
+  const R g0 = (eps + b0) * (eps + b0), g1 = (eps + b1) * (eps + b1), g2 = (eps + b2) * (eps + b2);
+  if constexpr (sizeof(R) == 8) {
+    // weights d_k / g_k scaled by g0 g1 g2: one division (products stay in
+    // range in FP64: g >= 1e-80)
+    const R a0 = R(0.1) * g1 * g2, a1 = R(0.6) * g0 * g2, a2 = R(0.3) * g0 * g1;
+    return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
+  } else {
+    const R a0 = R(0.1) / g0, a1 = R(0.6) / g1, a2 = R(0.3) / g2;
+    return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
+  }
+}
+
+// WENO5 face states of face m-1/2 from the six cells m-3 .. m+2 (p0..p5);
+// a face state with rho or p <= 0 falls back to its cell value.
+template <typename R>
+__device__ __forceinline__ void reconstruct_weno5(const R (&p0)[NV], const R (&p1)[NV],
+                                                  const R (&p2)[NV], const R (&p3)[NV],
+                                                  const R (&p4)[NV], const R (&p5)[NV],
+                                                  R (&wl)[NV], R (&wr)[NV]) {
+#pragma unroll
+  for (int v = 0; v < NV; ++v) {
+    wl[v] = weno5<R>(p0[v], p1[v], p2[v], p3[v], p4[v]);
+    wr[v] = weno5<R>(p5[v], p4[v], p3[v], p2[v], p1[v]);
+  }
+  if (!(wl[0] > R(0) && wl[4] > R(0)))
+#pragma unroll
+    for (int v = 0; v < NV; ++v) wl[v] = p2[v];
+  if (!(wr[0] > R(0) && wr[4] > R(0)))
+#pragma unroll
+    for (int v = 0; v < NV; ++v) wr[v] = p3[v];
 }
 
 // Numerical flux from the two face states: TVDLF

@@ -200,10 +200,20 @@ __global__ void __launch_bounds__(256) k_stage_v1(StageArgs<R> a) {
         load_prim(a, i - 1, j, k, w1);
         load_prim(a, i + 1, j, k, w3);
         load_prim(a, i + 2, j, k, w4);
-        reconstruct<R, LIM>(w0, w1, wc, w3, wl, wr);
-        face_flux<R, 1, FLUX>(wl, wr, a.gam, a.igm1, fm);
-        reconstruct<R, LIM>(w1, wc, w3, w4, wl, wr);
-        face_flux<R, 1, FLUX>(wl, wr, a.gam, a.igm1, fp);
+        if constexpr (LIM == LIM_WENO5) {
+          R wm3[NV], wp3[NV];
+          load_prim(a, i - 3, j, k, wm3);
+          load_prim(a, i + 3, j, k, wp3);
+          reconstruct_weno5<R>(wm3, w0, w1, wc, w3, w4, wl, wr);
+          face_flux<R, 1, FLUX>(wl, wr, a.gam, a.igm1, fm);
+          reconstruct_weno5<R>(w0, w1, wc, w3, w4, wp3, wl, wr);
+          face_flux<R, 1, FLUX>(wl, wr, a.gam, a.igm1, fp);
+        } else {
+          reconstruct<R, LIM>(w0, w1, wc, w3, wl, wr);
+          face_flux<R, 1, FLUX>(wl, wr, a.gam, a.igm1, fm);
+          reconstruct<R, LIM>(w1, wc, w3, w4, wl, wr);
+          face_flux<R, 1, FLUX>(wl, wr, a.gam, a.igm1, fp);
+        }
         const R rm2 = a.m.rm2[i], rp2 = a.m.rp2[i], ivr = a.m.ivr[i];
 #pragma unroll
         for (int v = 0; v < NV; ++v) L[v] -= (rp2 * fp[v] - rm2 * fm[v]) * ivr;
@@ -226,10 +236,23 @@ __global__ void __launch_bounds__(256) k_stage_v1(StageArgs<R> a) {
         if (f1) flip_theta(w1);
         if (f3) flip_theta(w3);
         if (f4) flip_theta(w4);
-        reconstruct<R, LIM>(w0, w1, wc, w3, wl, wr);
-        face_flux<R, 2, FLUX>(wl, wr, a.gam, a.igm1, fm);
-        reconstruct<R, LIM>(w1, wc, w3, w4, wl, wr);
-        face_flux<R, 2, FLUX>(wl, wr, a.gam, a.igm1, fp);
+        if constexpr (LIM == LIM_WENO5) {
+          R wm3[NV], wp3[NV];
+          bool fm3, fp3;
+          load_prim(a, i, mirror_row(j - 3, a.nt, fm3), k, wm3);
+          load_prim(a, i, mirror_row(j + 3, a.nt, fp3), k, wp3);
+          if (fm3) flip_theta(wm3);
+          if (fp3) flip_theta(wp3);
+          reconstruct_weno5<R>(wm3, w0, w1, wc, w3, w4, wl, wr);
+          face_flux<R, 2, FLUX>(wl, wr, a.gam, a.igm1, fm);
+          reconstruct_weno5<R>(w0, w1, wc, w3, w4, wp3, wl, wr);
+          face_flux<R, 2, FLUX>(wl, wr, a.gam, a.igm1, fp);
+        } else {
+          reconstruct<R, LIM>(w0, w1, wc, w3, wl, wr);
+          face_flux<R, 2, FLUX>(wl, wr, a.gam, a.igm1, fm);
+          reconstruct<R, LIM>(w1, wc, w3, w4, wl, wr);
+          face_flux<R, 2, FLUX>(wl, wr, a.gam, a.igm1, fp);
+        }
         const R sm = a.m.sm[j], sp = a.m.sp[j], ict = a.m.ict[j];
 #pragma unroll
         for (int v = 0; v < NV; ++v) L[v] -= hr * (sp * fp[v] - sm * fm[v]) * ict;
@@ -247,10 +270,20 @@ __global__ void __launch_bounds__(256) k_stage_v1(StageArgs<R> a) {
         load_prim(a, i, j, km1, w1);
         load_prim(a, i, j, kp1, w3);
         load_prim(a, i, j, kp2, w4);
-        reconstruct<R, LIM>(w0, w1, wc, w3, wl, wr);
-        face_flux<R, 3, FLUX>(wl, wr, a.gam, a.igm1, fm);
-        reconstruct<R, LIM>(w1, wc, w3, w4, wl, wr);
-        face_flux<R, 3, FLUX>(wl, wr, a.gam, a.igm1, fp);
+        if constexpr (LIM == LIM_WENO5) {
+          R wm3[NV], wp3[NV];
+          load_prim(a, i, j, ((k - 3) % np + np) % np, wm3);
+          load_prim(a, i, j, (k + 3) % np, wp3);
+          reconstruct_weno5<R>(wm3, w0, w1, wc, w3, w4, wl, wr);
+          face_flux<R, 3, FLUX>(wl, wr, a.gam, a.igm1, fm);
+          reconstruct_weno5<R>(w0, w1, wc, w3, w4, wp3, wl, wr);
+          face_flux<R, 3, FLUX>(wl, wr, a.gam, a.igm1, fp);
+        } else {
+          reconstruct<R, LIM>(w0, w1, wc, w3, wl, wr);
+          face_flux<R, 3, FLUX>(wl, wr, a.gam, a.igm1, fm);
+          reconstruct<R, LIM>(w1, wc, w3, w4, wl, wr);
+          face_flux<R, 3, FLUX>(wl, wr, a.gam, a.igm1, fp);
+        }
         const R f = hr * a.m.phf[j];
 #pragma unroll
         for (int v = 0; v < NV; ++v) L[v] -= f * (fp[v] - fm[v]);
@@ -319,12 +352,15 @@ void launch_stage(const StageArgs<R>& a, int stage, int flux, int lim, dim3 grid
                   hipStream_t s) {
   if (flux == FLUX_TVDLF) {
     if (lim == LIM_MINMOD) launch_stage_t<R, FLUX_TVDLF, LIM_MINMOD>(a, stage, grid, blk, s);
+    else if (lim == LIM_WENO5) launch_stage_t<R, FLUX_TVDLF, LIM_WENO5>(a, stage, grid, blk, s);
     else launch_stage_t<R, FLUX_TVDLF, LIM_MC>(a, stage, grid, blk, s);
   } else if (flux == FLUX_HLLD) {
     if (lim == LIM_MINMOD) launch_stage_t<R, FLUX_HLLD, LIM_MINMOD>(a, stage, grid, blk, s);
+    else if (lim == LIM_WENO5) launch_stage_t<R, FLUX_HLLD, LIM_WENO5>(a, stage, grid, blk, s);
     else launch_stage_t<R, FLUX_HLLD, LIM_MC>(a, stage, grid, blk, s);
   } else {
     if (lim == LIM_MINMOD) launch_stage_t<R, FLUX_HLL, LIM_MINMOD>(a, stage, grid, blk, s);
+    else if (lim == LIM_WENO5) launch_stage_t<R, FLUX_HLL, LIM_WENO5>(a, stage, grid, blk, s);
     else launch_stage_t<R, FLUX_HLL, LIM_MC>(a, stage, grid, blk, s);
   }
 }

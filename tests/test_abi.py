@@ -72,7 +72,7 @@ def test_workspace_size_and_validation(lib):
         (_grid(lib, n_r=2000, n_theta=2000, n_phi=1000), p),  # > 2^31 cells
         (_grid(lib, max_maps=0), p), (_grid(lib, max_probes=2, max_traj_pts=1), p),
         (g, _phys(lib, gamma=1.0)), (g, _phys(lib, cfl=0.0)), (g, _phys(lib, cfl=1.5)),
-        (g, _phys(lib, flux=7)), (g, _phys(lib, limiter=3)), (g, _phys(lib, precision=16)),
+        (g, _phys(lib, flux=7)), (g, _phys(lib, limiter=3)), (g, _phys(lib, limiter=4)), (g, _phys(lib, precision=16)),
         (g, _phys(lib, tracer=2)),
     ]
     for gg, pp in bad:
