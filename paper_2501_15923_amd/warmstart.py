@@ -69,14 +69,14 @@ def relaxed_states(grid, seeds, t_ref, precision=64, batch=64, chunk=4000):
         e.close()
 
 
-def build_dataset(net, grid, seeds, t_ref, rc, thc, precision=64):
+def build_dataset(net, grid, seeds, t_ref, rc, thc, precision=64, batch=64):
     import torch
     n = len(seeds)
     X = torch.empty((n, grid.nt, grid.np_, 8), dtype=torch.float32, device="cuda")
     T = torch.empty((n, grid.nt * grid.np_, 8 * grid.nr), dtype=torch.float32, device="cuda")
     M = torch.empty((n, 8, grid.nt, grid.np_), dtype=torch.float64, device="cuda")
     q = 0
-    for s, m, st in relaxed_states(grid, seeds, t_ref, precision):
+    for s, m, st in relaxed_states(grid, seeds, t_ref, precision, batch):
         dm = torch.from_numpy(m).cuda()
         M[q] = dm
         X[q] = net.encode_map(dm[None].contiguous(), thc, synth.OMEGA_SUN, grid.r_in)[0]
@@ -191,7 +191,11 @@ def main(argv=None):
     ap.add_argument("--phi-lo", type=int, default=None)
     ap.add_argument("--phi-hi", type=int, default=None)
     ap.add_argument("--lr", type=float, default=2e-3)
-    ap.add_argument("--crossings", type=float, default=2.0)
+    ap.add_argument("--crossings", type=float, default=2.0,
+                    help="reference relaxation length, slow-wind crossing times")
+    ap.add_argument("--data-crossings", type=float, default=None,
+                    help="relaxation length of the training targets (default: --crossings)")
+    ap.add_argument("--ens-batch", type=int, default=64, help="runs per ensemble launch")
     ap.add_argument("--data-precision", type=int, default=32)
     ap.add_argument("--out", default=None)
     ap.add_argument("--weights", default=None, help="evaluate these weights (skip training)")
@@ -223,7 +227,11 @@ def main(argv=None):
     else:
         train_seeds = list(range(TRAIN_SEED0, TRAIN_SEED0 + args.train))
         t0 = time.perf_counter()
-        X, T, _ = build_dataset(net, g, train_seeds, t_ref, rc, thc, args.data_precision)
+        t_data = t_ref if args.data_crossings is None else \
+            args.data_crossings * relax.slow_crossing_time(g)
+        report["data_t_days"] = t_data / 86400
+        X, T, _ = build_dataset(net, g, train_seeds, t_data, rc, thc, args.data_precision,
+                                args.ens_batch)
         report["dataset_seconds"] = time.perf_counter() - t0
         mean_t = T.mean(dim=0)
         net.set_params(p0)
