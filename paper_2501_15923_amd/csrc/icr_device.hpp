@@ -270,7 +270,7 @@ __device__ __forceinline__ void hlld_flux(const R (&wl0)[NV], const R (&wr0)[NV]
   auto rcp = [](R x) { return FAST ? rcp_fast(x) : R(1) / x; };
   const R bn = R(0.5) * (wl0[4 + N] + wr0[4 + N]);
   const R dbn = wr0[4 + N] - wl0[4 + N];
-  R w[2][NV], u[2][NV], f[2][NV];
+  R w[2][NV], u[2][NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
     w[0][v] = wl0[v];
@@ -278,18 +278,21 @@ __device__ __forceinline__ void hlld_flux(const R (&wl0)[NV], const R (&wr0)[NV]
   }
   w[0][4 + N] = bn;
   w[1][4 + N] = bn;
-#pragma unroll
-  for (int a = 0; a < 2; ++a) {
-    prim2cons<R>(w[a], u[a], igm1);
-    phys_flux<R, N>(w[a], u[a], f[a]);
-  }
+  prim2cons<R>(w[0], u[0], igm1);
+  prim2cons<R>(w[1], u[1], igm1);
   const R cmax = rmax(cfast<R, N, FAST>(w[0], gam), cfast<R, N, FAST>(w[1], gam));
   const R sl = rmin(w[0][N], w[1][N]) - cmax, sr = rmax(w[0][N], w[1][N]) + cmax;
   const R fbn = (sl < R(0) && sr > R(0)) ? sl * sr * dbn * rcp(sr - sl) : R(0);
+  // every region's flux needs the physical flux of one side only
   if (sl >= R(0) || sr <= R(0)) {
     const bool left = sl >= R(0);
+    R wa[NV], ua[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) fs[v] = left ? f[0][v] : f[1][v];
+    for (int v = 0; v < NV; ++v) {
+      wa[v] = left ? w[0][v] : w[1][v];
+      ua[v] = left ? u[0][v] : u[1][v];
+    }
+    phys_flux<R, N>(wa, ua, fs);
     fs[4 + N] = fbn;
     return;
   }
@@ -302,7 +305,7 @@ __device__ __forceinline__ void hlld_flux(const R (&wl0)[NV], const R (&wr0)[NV]
   const R idd = rcp(d[1] - d[0]);
   const R sm = (d[1] * w[1][N] - d[0] * w[0][N] - pt[1] + pt[0]) * idd;
   const R pts = (d[1] * pt[0] - d[0] * pt[1] + d[0] * d[1] * (w[1][N] - w[0][N])) * idd;
-  // outer star states and their fluxes F*_a = F_a + S_a (U*_a - U_a)
+  // outer star states of both sides (the double-star state needs both)
   R us[2][NV], sq[2];
 #pragma unroll
   for (int a = 0; a < 2; ++a) {
@@ -331,18 +334,31 @@ __device__ __forceinline__ void hlld_flux(const R (&wl0)[NV], const R (&wr0)[NV]
     us[a][4 + T1] = bt1;
     us[a][4 + T2] = bt2;
     sq[a] = FAST ? sqrt_fast(rho) : sqrt(rho);
+  }
+  // the side of the contact the face lies on: F*_a = F_a + S_a (U*_a - U_a)
+  const bool left = sm >= R(0);
+  R q[NV], fa[NV];
+  {
+    R wa[NV], ua[NV];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) f[a][v] += s * (us[a][v] - u[a][v]);
+    for (int v = 0; v < NV; ++v) {
+      wa[v] = left ? w[0][v] : w[1][v];
+      ua[v] = left ? u[0][v] : u[1][v];
+      q[v] = left ? us[0][v] : us[1][v];
+    }
+    phys_flux<R, N>(wa, ua, fa);
+    const R sa = left ? sl : sr;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) fa[v] += sa * (q[v] - ua[v]);
   }
   const R ssl = sm - fabs(bn) * rcp(sq[0]), ssr = sm + fabs(bn) * rcp(sq[1]);
   if (ssl >= R(0) || ssr <= R(0)) {
-    const bool left = ssl >= R(0);
 #pragma unroll
-    for (int v = 0; v < NV; ++v) fs[v] = left ? f[0][v] : f[1][v];
+    for (int v = 0; v < NV; ++v) fs[v] = fa[v];
     fs[4 + N] = fbn;
     return;
   }
-  // double-star state on the side of the contact the face lies on
+  // double-star state between the rotational waves
   const R sg = bn >= R(0) ? R(1) : R(-1);
   const R isq = rcp(sq[0] + sq[1]);
   const R vl1 = us[0][T1] / us[0][0], vl2 = us[0][T2] / us[0][0];
@@ -353,13 +369,6 @@ __device__ __forceinline__ void hlld_flux(const R (&wl0)[NV], const R (&wr0)[NV]
                isq;
   const R b2 = (sq[0] * us[1][4 + T2] + sq[1] * us[0][4 + T2] + sq[0] * sq[1] * (vr2 - vl2) * sg) *
                isq;
-  const bool left = sm >= R(0);
-  R q[NV], fa[NV];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    q[v] = left ? us[0][v] : us[1][v];
-    fa[v] = left ? f[0][v] : f[1][v];
-  }
   const R vbs = (q[N] * q[4 + N] + q[T1] * q[4 + T1] + q[T2] * q[4 + T2]) / q[0];
   const R vbss = sm * bn + v1 * b1 + v2 * b2;
   R uss[NV];

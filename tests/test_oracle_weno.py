@@ -75,8 +75,8 @@ def test_brio_wu_self_convergence(orc):
         run_to(o, 0.1)
         return get_1d(o)[0]
 
-    ref = run(2048)
-    errs = [np.mean(np.abs(run(n) - ref.reshape(n, -1).mean(axis=1))) for n in (128, 256, 512)]
+    ref = run(1024)
+    errs = [np.mean(np.abs(run(n) - ref.reshape(n, -1).mean(axis=1))) for n in (64, 128, 256)]
     assert errs[0] > errs[1] > errs[2] and errs[2] < 0.01, errs
 
 
