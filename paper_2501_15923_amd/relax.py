@@ -33,10 +33,12 @@ def _sync():
     torch.cuda.synchronize()
 
 
-def plain_with_reference(solver, t_ref, chunk=100, r_shell=AU, tol_resid=1e-4, tol_shell=0.02):
+def plain_with_reference(solver, t_ref, chunk=100, r_shell=AU, tol_resid=1e-4, tol_shell=0.02,
+                         progress=None):
     """Plain relaxation up to t_ref, recording (steps, wall, residual, shell)
     after every chunk; the final shell is the reference, and the first chunk
-    meeting both criteria against it gives the plain steps and wall time."""
+    meeting both criteria against it gives the plain steps and wall time.
+    progress, if given, is called with (steps, wall) after every chunk."""
     hist = []
     steps, wall = 0, 0.0
     while True:
@@ -47,6 +49,8 @@ def plain_with_reference(solver, t_ref, chunk=100, r_shell=AU, tol_resid=1e-4, t
         wall += time.perf_counter() - t0
         steps += info["steps"]
         hist.append((steps, wall, info["resid"], sh))
+        if progress is not None:
+            progress(steps, wall)
         if info["steps"] < chunk:
             break
     ref = hist[-1][3]
@@ -68,9 +72,10 @@ def first_relaxed(rec, tol_resid, tol_shell):
 
 
 def relax(solver, ref_shell, t_max, chunk=100, r_shell=AU, tol_resid=1e-4, tol_shell=0.02,
-          wall0=0.0, max_steps=1 << 40):
+          wall0=0.0, max_steps=1 << 40, progress=None):
     """Step from the current state until both criteria hold (or t_max, or
-    max_steps); the record keeps (steps, wall, resid, err_rho, err_vr) per chunk."""
+    max_steps); the record keeps (steps, wall, resid, err_rho, err_vr) per chunk.
+    progress, if given, is called with (steps, wall) after every chunk."""
     steps, wall = 0, wall0
     rec = []
     while True:
@@ -81,6 +86,8 @@ def relax(solver, ref_shell, t_max, chunk=100, r_shell=AU, tol_resid=1e-4, tol_s
         wall += time.perf_counter() - t0
         steps += info["steps"]
         rec.append((steps, wall, info["resid"]) + shell_errors(sh, ref_shell))
+        if progress is not None:
+            progress(steps, wall)
         out = first_relaxed(rec[-1:], tol_resid, tol_shell)
         if out["converged"] or info["steps"] < chunk or steps >= max_steps:
             out["history"] = rec

@@ -58,6 +58,8 @@ def relaxed_states(grid, seeds, t_ref, precision=64, batch=64, chunk=4000):
         while True:
             info = e.step(chunk, t_end=t_ref, raise_on_error=False)
             failed |= {q for q, i in enumerate(info) if i["status"] != 0}
+            log(f"warmstart: batch at {b0}: t = {min(i['t'] for i in info) / 86400:.2f} d "
+                f"after {time.perf_counter() - t0:.1f} s")
             if max(i["steps"] for i in info) < chunk:
                 break
         log(f"warmstart: relaxed {len(sub)} maps to {t_ref / 86400:.1f} d in "
@@ -127,13 +129,23 @@ def evaluate(net, grid, seeds, t_ref, predictors, chunk=50, precision=64):
 
     from .solver import Solver
     rows = []
+
+    def ticker(label):
+        last = [time.perf_counter()]
+
+        def f(steps, wall):
+            if time.perf_counter() - last[0] > 30.0:
+                last[0] = time.perf_counter()
+                log(f"warmstart: {label}: {steps} steps, {wall:.1f} s")
+        return f
+
     for s in seeds:
         m = synth.relax_map(grid, s)
         solver = Solver(grid, precision=precision)
         solver.set_maps(np.zeros(1), m[None])
         solver.init_radial()
         rc, thc = grid_geometry(solver)
-        plain = relax.plain_with_reference(solver, t_ref, chunk)
+        plain = relax.plain_with_reference(solver, t_ref, chunk, progress=ticker(f"seed {s} plain"))
         row = dict(seed=s, plain=dict((k, v) for k, v in plain.items() if k != "ref"))
         dm = torch.from_numpy(m).cuda()
         for name, pred in predictors.items():
@@ -146,7 +158,8 @@ def evaluate(net, grid, seeds, t_ref, predictors, chunk=50, precision=64):
             solver.set_state(st)
             torch.cuda.synchronize()
             w0 = time.perf_counter() - t0
-            res = relax.relax(solver, plain["ref"], t_ref, chunk, wall0=w0)
+            res = relax.relax(solver, plain["ref"], t_ref, chunk, wall0=w0,
+                              progress=ticker(f"seed {s} {name}"))
             res["init_wall"] = w0
             row[name] = res
         solver.close()
@@ -200,6 +213,8 @@ def main(argv=None):
     ap.add_argument("--out", default=None)
     ap.add_argument("--weights", default=None, help="evaluate these weights (skip training)")
     ap.add_argument("--report", default=None)
+    ap.add_argument("--no-ablations", action="store_true",
+                    help="evaluate the trained network only (no untrained / mean-state starts)")
     args = ap.parse_args(argv)
     import torch
 
@@ -252,8 +267,9 @@ def main(argv=None):
             return net.forward(x)
         return f
     preds["warm"] = with_params(p)
-    preds["untrained"] = with_params(p0)
-    preds["mean_target"] = lambda x: mean_t
+    if not args.no_ablations:
+        preds["untrained"] = with_params(p0)
+        preds["mean_target"] = lambda x: mean_t
     test_seeds = list(range(TEST_SEED0, TEST_SEED0 + args.test))
     rows = evaluate(net, g, test_seeds, t_ref, preds)
     report["summary"] = summarise(rows, list(preds))
