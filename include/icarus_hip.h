@@ -82,7 +82,8 @@ enum {
  * capacities size the workspace: boundary maps, cone CMEs, probes, points
  * per trajectory table and rows of the device probe log. */
 typedef struct {
-  int n_r, n_theta, n_phi;
+  int n_r, n_theta, n_phi;   /* >= 1 each, product < 2^29 (one variable's
+                                array below 4 GiB)                      */
   double r_in, r_out;        /* m, 0 < r_in < r_out                     */
   double th_min, th_max;     /* rad, 0 < th_min < th_max < pi           */
   int max_maps;              /* >= 1                                     */

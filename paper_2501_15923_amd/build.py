@@ -19,6 +19,10 @@ HEADERS = [os.path.join(PKG, "csrc", f) for f in ("icr_kernels.hpp", "icr_device
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
+    # multiply-adds fused only within one source expression: every copy of an
+    # expression the compiler makes (peeled iterations, other kernels) rounds
+    # the same way, so tilings, plane chunks and ensemble runs agree bitwise
+    "-ffp-contract=on",
     # no packed-FP32 instructions in device code
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
 ]

@@ -134,7 +134,9 @@ int validate(const icr_grid* g, const icr_phys* p) {
     return fail(ICR_ERR_ARG, "cell counts must be >= 1 (got %d %d %d)", g->n_r, g->n_theta,
                 g->n_phi);
   const double cells = (double)g->n_r * g->n_theta * g->n_phi;
-  if (cells >= 2147483647.0) return fail(ICR_ERR_ARG, "grid too large (%.0f cells)", cells);
+  // the stage kernels address one variable's array with 32-bit byte offsets
+  if (cells >= 536870912.0)
+    return fail(ICR_ERR_ARG, "grid too large (%.0f cells, at most 2^29 - 1)", cells);
   if (!(g->r_in > 0 && g->r_out > g->r_in))
     return fail(ICR_ERR_ARG, "need 0 < r_in < r_out");
   if (!(g->th_min > 0 && g->th_max > g->th_min && g->th_max < kPi))
@@ -1098,7 +1100,7 @@ RunDesc<R> make_desc(icr_solver* s, int planes) {
   d.ghost1 = (R*)s->ghost(1);
   d.clock = s->clock();
   d.partials = (double*)(s->ws + s->L.partials);
-  d.nbx = (s->g.n_r + 63) / 64;
+  d.nbx = (s->g.n_r + tile_cells_r(64) - 1) / tile_cells_r(64);
   d.nby = (s->g.n_theta + 3) / 4;
   d.nbz = (s->g.n_phi + planes - 1) / planes;
   d.planes = planes;

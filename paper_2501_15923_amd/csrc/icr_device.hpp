@@ -46,6 +46,20 @@ struct Metric {
   R ilth;                                                 // 1 / dtheta
 };
 
+// Element idx of a device array: a 32-bit byte offset from a wave-uniform
+// base (the grid setup keeps every array below 4 GiB).  Loads of several
+// arrays at the same index then share one offset register instead of each
+// holding a 64-bit address.
+template <typename T>
+__device__ __forceinline__ T ldg(const T* base, unsigned idx) {
+  return *reinterpret_cast<const T*>(reinterpret_cast<const char*>(base) +
+                                     idx * (unsigned)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ void stg(T* base, unsigned idx, T x) {
+  *reinterpret_cast<T*>(reinterpret_cast<char*>(base) + idx * (unsigned)sizeof(T)) = x;
+}
+
 // Reflecting colatitude edges: a row index beyond [0, nt) reads the mirror
 // row (-1 - j below, 2 nt - 1 - j above, clamped to the grid) with the theta
 // components of velocity and field negated (flip = true).
@@ -432,23 +446,23 @@ __device__ __forceinline__ void add_sources(const R (&w)[NV], const Metric<R>& m
                                             R omega, int gravity, int corot, R (&L)[NV]) {
   const R rho = w[0], vr = w[1], vt = w[2], vp = w[3], p = w[4];
   const R br = w[5], bt = w[6], bp = w[7];
-  const R irc = m.irc[i];
-  const R cot = m.cot[j];
+  const R irc = ldg(m.irc, i);
+  const R cot = ldg(m.cot, j);
   const R ptot = p + R(0.5) * (br * br + bt * bt + bp * bp);
-  L[1] += (rho * (vt * vt + vp * vp) - (bt * bt + bp * bp)) * irc + ptot * m.gr[i];
+  L[1] += (rho * (vt * vt + vp * vp) - (bt * bt + bp * bp)) * irc + ptot * ldg(m.gr, i);
   L[2] += (-(rho * vr * vt - br * bt) + cot * (rho * vp * vp - bp * bp)) * irc +
-          ptot * m.hr[i] * cot;
+          ptot * ldg(m.hr, i) * cot;
   L[3] -= ((rho * vp * vr - bp * br) + cot * (rho * vp * vt - bp * bt)) * irc;
   L[6] += (vr * bt - vt * br) * irc;
   L[7] += ((vr * bp - vp * br) + cot * (vt * bp - vp * bt)) * irc;
   if (gravity) {
-    const R g = m.grav[i];
+    const R g = ldg(m.grav, i);
     L[1] += rho * g;
     L[4] += rho * vr * g;
   }
   if (corot) {
-    const R sn = m.snc[j], cs = m.csc[j];
-    const R r = m.rc[i];
+    const R sn = ldg(m.snc, j), cs = ldg(m.csc, j);
+    const R r = ldg(m.rc, i);
     const R cen = rho * omega * omega * r * sn;
     const R cor = R(2) * rho * omega;
     L[1] += cen * sn + cor * vp * sn;

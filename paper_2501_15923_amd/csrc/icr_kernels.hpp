@@ -180,9 +180,9 @@ __device__ __forceinline__ void write_partials(double* partials, int bid, double
 template <typename R, bool FAST = false>
 __device__ __forceinline__ double cell_rate(const R (&w)[NV], const Metric<R>& m, int i, int j,
                                             R gam) {
-  const R lr = (fabs(w[1]) + cfast<R, 1, FAST>(w, gam)) * m.idr[i];
-  const R lt = (fabs(w[2]) + cfast<R, 2, FAST>(w, gam)) * m.irc[i] * m.ilth;
-  const R lp = (fabs(w[3]) + cfast<R, 3, FAST>(w, gam)) * m.irc[i] * m.ilph[j];
+  const R lr = (fabs(w[1]) + cfast<R, 1, FAST>(w, gam)) * ldg(m.idr, i);
+  const R lt = (fabs(w[2]) + cfast<R, 2, FAST>(w, gam)) * ldg(m.irc, i) * m.ilth;
+  const R lp = (fabs(w[3]) + cfast<R, 3, FAST>(w, gam)) * ldg(m.irc, i) * ldg(m.ilph, j);
   return (double)(lr + lt + lp);
 }
 
@@ -357,6 +357,9 @@ void launch_shell(const void* u, const double* rc, int nr, int nt, int np, doubl
 template <typename R>
 void launch_stage_lds(const StageArgs<R>& a, int stage, int flux, int lim, int tile_r,
                       int kplanes, hipStream_t s);
+// Cells along r updated by a face-once tile of tile_r lanes: two lanes on
+// each side carry the r halo.
+__host__ __device__ constexpr int tile_cells_r(int tile_r) { return tile_r - 4; }
 long long stage_lds_blocks(int nr, int nt, int np, int tile_r, int kplanes);
 template <typename R>
 void launch_finalize(DevClock* ck, const double* part, int nblocks, double cfl, int advance,

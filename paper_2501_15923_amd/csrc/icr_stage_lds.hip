@@ -22,7 +22,8 @@ k_stage_lds(StageArgs<R> a, int kplanes) {
 
 template <typename R, int TR, int TT, int FLUX, int LIM, bool FM>
 static void launch_lds_t(const StageArgs<R>& a, int stage, int kplanes, hipStream_t s) {
-  const dim3 grid((a.nr + TR - 1) / TR, (a.nt + TT - 1) / TT, (a.np + kplanes - 1) / kplanes);
+  constexpr int TI = tile_cells_r(TR);
+  const dim3 grid((a.nr + TI - 1) / TI, (a.nt + TT - 1) / TT, (a.np + kplanes - 1) / kplanes);
   const dim3 blk(TR, TT);
   if (stage == 1)
     hipLaunchKernelGGL((k_stage_lds<R, TR, TT, FLUX, LIM, 1, FM>), grid, blk, 0, s, a, kplanes);
@@ -69,8 +70,8 @@ template void launch_stage_lds<float>(const StageArgs<float>&, int, int, int, in
                                       hipStream_t);
 
 long long stage_lds_blocks(int nr, int nt, int np, int tile_r, int kplanes) {
-  const int tt = 256 / tile_r;
-  return (long long)((nr + tile_r - 1) / tile_r) * ((nt + tt - 1) / tt) *
+  const int tt = 256 / tile_r, ti = tile_cells_r(tile_r);
+  return (long long)((nr + ti - 1) / ti) * ((nt + tt - 1) / tt) *
          ((np + kplanes - 1) / kplanes);
 }
 

@@ -4,11 +4,13 @@
 //
 // One RK2 stage of the finite-volume update (Sect. 2 Eqs. 1-6) with every
 // face flux computed exactly once:
-//   - a block owns a TR x TT tile of (r, theta) columns and marches along
-//     phi over a chunk of planes;
-//   - per plane the primitives of the tile plus a two-cell halo in r and
-//     theta sit in LDS; r- and theta-face fluxes go to LDS and are shared by
-//     the two cells of each face;
+//   - a block of TR x TT threads marches along phi over a chunk of planes;
+//     each row of TR lanes covers TR - 4 cells of the tile plus the two-cell
+//     r halo on either side (the halo lanes load and convert their cells
+//     like every other lane, so the r halo costs no extra loads);
+//   - per plane the primitives of the tile's rows plus a two-row theta halo
+//     sit in LDS; r- and theta-face fluxes go to LDS and are shared by the
+//     two cells of each face;
 //   - the phi direction is carried in registers: each thread keeps the
 //     primitives of planes k-1 .. k+2 of its own column and the flux of
 //     face k-1/2 from the previous plane.
@@ -23,10 +25,10 @@ namespace icr {
 
 
 template <typename R, bool FAST>
-__device__ __forceinline__ void load_cons_prim(const StageArgs<R>& a, long long c, R (&w)[NV]) {
+__device__ __forceinline__ void load_cons_prim(const StageArgs<R>& a, unsigned c, R (&w)[NV]) {
   R u[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) u[v] = a.uin[v * a.ncell + c];
+  for (int v = 0; v < NV; ++v) u[v] = ldg(a.uin + v * a.ncell, c);
   cons2prim<R, FAST>(u, w, a.gm1);
 }
 
@@ -48,15 +50,18 @@ __device__ __forceinline__ void lds_face(const R* base, int stride, R gam, R igm
   face_flux<R, N, FLUX, true>(wl, wr, gam, igm1, f);
 }
 
-// One tile (bx, by, bz) of one run: TR x TT columns, planes bz*kplanes ..;
-// stage-2 partials go to slot pslot.  Called by the single-run kernel and by
-// the ensemble kernels, so both execute the same code.
-// LDS of one tile: primitives with a two-cell halo, r-face and theta-face
-// fluxes.  Declared once per kernel and passed to stage_tile.
+// One tile (bx, by, bz) of one run: (TR - 4) x TT columns, planes
+// bz*kplanes ..; stage-2 partials go to slot pslot.  Called by the
+// single-run kernel and by the ensemble kernels, so both execute the same
+// code.
+// LDS of one tile, indexed by lane along r (lane l holds cell i0 + l - 2):
+// primitives of rows -2 .. TT+1, the flux of r face i-1/2 at the lane of
+// cell i, the flux of theta face j-1/2 at row j (0 .. TT).  Declared once
+// per kernel and passed to stage_tile.
 template <typename R, int TR, int TT>
 struct StageSmem {
-  R sW[NV][TT + 4][TR + 4];
-  R sFr[NV][TT][TR + 1];
+  R sW[NV][TT + 4][TR];
+  R sFr[NV][TT][TR];
   R sFt[NV][TT + 1][TR];
 };
 
@@ -66,32 +71,46 @@ template <typename R, int TR, int TT, int FLUX, int LIM, int STAGE, bool FM = fa
 __device__ __forceinline__ void stage_tile(const StageArgs<R>& a, int kplanes, int bx, int by,
                                            int bz, int pslot, StageSmem<R, TR, TT>& sm) {
   constexpr int NT = TR * TT;
-  constexpr int WR = TR + 4, WT = TT + 4;
+  constexpr int TI = tile_cells_r(TR);
+  constexpr int WT = TT + 4;
   auto& sW = sm.sW;
   auto& sFr = sm.sFr;
   auto& sFt = sm.sFt;
 
   const int ti = threadIdx.x, tj = threadIdx.y, tid = tj * TR + ti;
-  const int i0 = bx * TR, j0 = by * TT, k0 = bz * kplanes;
+  const int i0 = bx * TI, j0 = by * TT, k0 = bz * kplanes;
   const int nr = a.nr, nt = a.nt, np = a.np;
   const int kend = k0 + kplanes < np ? k0 + kplanes : np;
-  const int i = i0 + ti, j = j0 + tj;
-  const bool valid = i < nr && j < nt;
-  const int ic = i < nr ? i : nr - 1, jc = j < nt ? j : nt - 1;
+  const int i = i0 + ti - 2, j = j0 + tj;  // this lane's cell
+  const bool inner = ti >= 2 && ti < TR - 2;
+  const bool valid = inner && i < nr && j < nt;
+  const int ic = i < 0 ? 0 : (i < nr ? i : nr - 1), jc = j < nt ? j : nt - 1;
   const int active = a.clock->active;
-  const long long colbase = (long long)jc * nr + ic;  // + k * nt * nr
+  // cell offsets within one variable's array (32-bit: below 2^29 cells)
+  const unsigned colbase = (unsigned)(jc * nr + ic);  // + k * nt * nr
   // own-column loads: rows past the last colatitude mirror it (they serve
-  // as ghost rows of the last active row's upper theta face)
+  // as ghost rows of the last active row's upper theta face); cells below
+  // r_in (halo lanes of the first tile) come from the inner ghost, cells
+  // beyond r_out repeat the last cell
   bool flipj;
-  const long long lbase = (long long)mirror_row(j, nt, flipj) * nr + ic;
-  const long long plane_cells = (long long)nt * nr;
+  const int mj = mirror_row(j, nt, flipj);
+  const unsigned lbase = (unsigned)(mj * nr + ic);
+  const bool lghost = i < 0;
+  const unsigned plane_cells = (unsigned)(nt * nr);
+  const long long gplane = (long long)nt * np;
+  // The ring of the first tile's two halo lanes below r_in holds cell 0;
+  // those lanes put the inner ghost into LDS instead (see below).
+  auto load_own = [&](int k, R (&w)[NV]) {
+    load_cons_prim<R, true>(a, (unsigned)wrap_phi(k, np) * plane_cells + lbase, w);
+    if (flipj) flip_theta(w);
+  };
 
   if (!active) {
     if (STAGE == 2 && valid)
       for (int k = k0; k < kend; ++k) {
-        const long long c = (long long)k * plane_cells + colbase;
+        const unsigned c = (unsigned)k * plane_cells + colbase;
 #pragma unroll
-        for (int v = 0; v < NV; ++v) a.uout[v * a.ncell + c] = a.un[v * a.ncell + c];
+        for (int v = 0; v < NV; ++v) stg(a.uout + v * a.ncell, c, ldg(a.un + v * a.ncell, c));
       }
     return;
   }
@@ -100,82 +119,76 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R>& a, int kplanes, i
   // wb = W(k), wc = W(k+1) and fcar = flux of face k-1/2.  Iteration k0-1
   // only forms fcar, through the same code as every later phi face.
   R wa[NV], wb[NV], wc[NV], fcar[NV];
-  load_cons_prim<R, true>(a, (long long)wrap_phi(k0 - 2, np) * plane_cells + lbase, wa);
-  load_cons_prim<R, true>(a, (long long)wrap_phi(k0 - 1, np) * plane_cells + lbase, wb);
-  load_cons_prim<R, true>(a, (long long)wrap_phi(k0, np) * plane_cells + lbase, wc);
-  if (flipj) {
-    flip_theta(wa);
-    flip_theta(wb);
-    flip_theta(wc);
-  }
+  load_own(k0 - 2, wa);
+  load_own(k0 - 1, wb);
+  load_own(k0, wc);
 #pragma unroll
   for (int v = 0; v < NV; ++v) fcar[v] = R(0);
 
   double lam = 0.0, s1 = 0.0, s0 = 0.0;
   int bad = BAD_NONE;
-  const long long gplane = (long long)nt * np;
 
   for (int k = k0 - 1; k < kend; ++k) {
     const bool body = k >= k0;  // uniform over the block
-    const long long kbase = (long long)k * plane_cells;
+    const unsigned kbase = (unsigned)k * plane_cells;
     if (body) {
       __syncthreads();  // the previous plane's LDS reads are complete
+      if (lghost) {  // inner ghost (primitives) at this lane's row
+        R w[NV];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) sW[v][tj + 2][ti + 2] = wb[v];
-      for (int h = tid; h < 4 * TR + 4 * TT; h += NT) {
-        int ii, jj;
-        if (h < 4 * TR) {
-          const int row = h / TR;
-          ii = h - row * TR;
-          jj = row < 2 ? row - 2 : TT + row - 2;
-        } else {
-          const int q = h - 4 * TR, s = q / TT;
-          jj = q - s * TT;
-          ii = s < 2 ? s - 2 : TR + s - 2;
-        }
-        int gi = i0 + ii;
+        for (int v = 0; v < NV; ++v) w[v] = ldg(a.ghost + v * gplane, (unsigned)(k * nt + mj));
+        if (flipj) flip_theta(w);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sW[v][tj + 2][ti] = w[v];
+      } else {
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sW[v][tj + 2][ti] = wb[v];
+      }
+      // theta halo: rows -2, -1, TT, TT + 1 over all TR lanes
+      for (int h = tid; h < 4 * TR; h += NT) {
+        const int row = h / TR, l = h - row * TR;
+        const int jj = row < 2 ? row - 2 : TT + row - 2;
+        const int gi = i0 + l - 2;
         bool flip;
         const int gj = mirror_row(j0 + jj, nt, flip);
         R w[NV];
         if (gi < 0) {
-          const long long g = (long long)k * nt + gj;
+          const unsigned g = (unsigned)(k * nt + gj);
 #pragma unroll
-          for (int v = 0; v < NV; ++v) w[v] = a.ghost[v * gplane + g];
+          for (int v = 0; v < NV; ++v) w[v] = ldg(a.ghost + v * gplane, g);
         } else {
-          gi = gi >= nr ? nr - 1 : gi;
-          load_cons_prim<R, true>(a, kbase + (long long)gj * nr + gi, w);
+          load_cons_prim<R, true>(a, kbase + (unsigned)(gj * nr + (gi < nr ? gi : nr - 1)), w);
         }
         if (flip) flip_theta(w);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) sW[v][jj + 2][ii + 2] = w[v];
+        for (int v = 0; v < NV; ++v) sW[v][jj + 2][l] = w[v];
       }
       __syncthreads();
-      // r face i-1/2 and theta face j-1/2 of each cell, plus the tile's
-      // last r face of every row and last theta face of every column
-      constexpr int VS = WT * WR;
+      // r face i-1/2 and theta face j-1/2 at every lane (the update reads
+      // the r faces of lanes 2 .. TR-2, the last being the tile's upper r
+      // face, and the theta faces of the inner lanes; the others are never
+      // read, and lanes 0, 1 and TR-1 read neighbouring LDS rows for their
+      // r face), then the tile's upper theta face of every inner lane
+      constexpr int VS = WT * TR;
       {
         R f[NV];
-        lds_face<R, 1, FLUX, LIM>(&sW[0][tj + 2][ti], 1, a.gam, a.igm1, f, VS);
+        lds_face<R, 1, FLUX, LIM>(&sW[0][tj + 2][ti] - 2, 1, a.gam, a.igm1, f, VS);
 #pragma unroll
         for (int v = 0; v < NV; ++v) sFr[v][tj][ti] = f[v];
       }
       {
         R f[NV];
-        lds_face<R, 2, FLUX, LIM>(&sW[0][tj][ti + 2], WR, a.gam, a.igm1, f, VS);
+        lds_face<R, 2, FLUX, LIM>(&sW[0][tj][ti], TR, a.gam, a.igm1, f, VS);
 #pragma unroll
         for (int v = 0; v < NV; ++v) sFt[v][tj][ti] = f[v];
       }
-      if (tid < TT) {
-        R f[NV];
-        lds_face<R, 1, FLUX, LIM>(&sW[0][tid + 2][TR], 1, a.gam, a.igm1, f, VS);
-#pragma unroll
-        for (int v = 0; v < NV; ++v) sFr[v][tid][TR] = f[v];
-      }
       for (int q = tid - 64; q >= 0 && q < TR; q += NT - 64) {
-        R f[NV];
-        lds_face<R, 2, FLUX, LIM>(&sW[0][TT][q + 2], WR, a.gam, a.igm1, f, VS);
+        if (q >= 2 && q < TR - 2) {
+          R f[NV];
+          lds_face<R, 2, FLUX, LIM>(&sW[0][TT][q], TR, a.gam, a.igm1, f, VS);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) sFt[v][TT][q] = f[v];
+          for (int v = 0; v < NV; ++v) sFt[v][TT][q] = f[v];
+        }
       }
     }
     // The own cell's conserved values for the update (and, in stage 2, those
@@ -183,20 +196,19 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R>& a, int kplanes, i
     // their latency overlaps that work instead of stalling the update.
     R uc[NV], up[NV];
     if (body && valid) {
-      const long long c = kbase + colbase;
+      const unsigned c = kbase + colbase;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) uc[v] = a.uin[v * a.ncell + c];
+      for (int v = 0; v < NV; ++v) uc[v] = ldg(a.uin + v * a.ncell, c);
       if (STAGE == 2) {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) up[v] = a.un[v * a.ncell + c];
+        for (int v = 0; v < NV; ++v) up[v] = ldg(a.un + v * a.ncell, c);
       }
     }
     // phi face k+1/2 from the register ring (and the next plane's load)
     R fhi[NV];
     {
       R wd[NV], wl[NV], wr[NV];
-      load_cons_prim<R, true>(a, (long long)wrap_phi(k + 2, np) * plane_cells + lbase, wd);
-      if (flipj) flip_theta(wd);
+      load_own(k + 2, wd);
       reconstruct<R, LIM, true>(wa, wb, wc, wd, wl, wr);
       face_flux<R, 3, FLUX, true>(wl, wr, a.gam, a.igm1, fhi);
 #pragma unroll
@@ -210,9 +222,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R>& a, int kplanes, i
     if (body) {
       __syncthreads();  // r / theta face fluxes are in LDS
       if (valid) {
-        const R rm2 = a.m.rm2[ic], rp2 = a.m.rp2[ic], ivr = a.m.ivr[ic], hr = a.m.hr[ic];
-        const R sm = a.m.sm[jc], sp = a.m.sp[jc], ict = a.m.ict[jc];
-        const R fph = hr * a.m.phf[jc];
+        const R rm2 = ldg(a.m.rm2, ic), rp2 = ldg(a.m.rp2, ic), ivr = ldg(a.m.ivr, ic);
+        const R hr = ldg(a.m.hr, ic);
+        const R sm = ldg(a.m.sm, jc), sp = ldg(a.m.sp, jc), ict = ldg(a.m.ict, jc);
+        const R fph = hr * ldg(a.m.phf, jc);
         R L[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
@@ -223,24 +236,24 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R>& a, int kplanes, i
         }
         add_sources<R>(wa, a.m, ic, jc, a.omega, a.gravity, a.corot, L);
         const R dt = (R)a.clock->dt;
-        const long long c = kbase + colbase;
+        const unsigned c = kbase + colbase;
         if constexpr (FM) {  // passive tracer on: keep this stage's mass fluxes
-          a.fmass[c] = sFr[0][tj][ti];
-          a.fmass[a.ncell + c] = sFt[0][tj][ti];
-          a.fmass[2 * a.ncell + c] = fcar[0];
-          if (i == nr - 1) a.fmass_rout[(long long)k * nt + j] = sFr[0][tj][ti + 1];
-          if (j == nt - 1) a.fmass_tend[(long long)k * nr + i] = sFt[0][tj + 1][ti];
+          stg(a.fmass, c, sFr[0][tj][ti]);
+          stg(a.fmass + a.ncell, c, sFt[0][tj][ti]);
+          stg(a.fmass + 2 * a.ncell, c, fcar[0]);
+          if (i == nr - 1) stg(a.fmass_rout, (unsigned)(k * nt + j), sFr[0][tj][ti + 1]);
+          if (j == nt - 1) stg(a.fmass_tend, (unsigned)(k * nr + i), sFt[0][tj + 1][ti]);
         }
         if (STAGE == 1) {
 #pragma unroll
-          for (int v = 0; v < NV; ++v) a.uout[v * a.ncell + c] = uc[v] + dt * L[v];
+          for (int v = 0; v < NV; ++v) stg(a.uout + v * a.ncell, c, uc[v] + dt * L[v]);
         } else {
           R un[NV], unew[NV], wn[NV];
 #pragma unroll
           for (int v = 0; v < NV; ++v) {
             un[v] = up[v];
             unew[v] = R(0.5) * un[v] + R(0.5) * (uc[v] + dt * L[v]);
-            a.uout[v * a.ncell + c] = unew[v];
+            stg(a.uout + v * a.ncell, c, unew[v]);
           }
           cons2prim<R, true>(unew, wn, a.gm1);
           lam = fmax(lam, cell_rate<R, true>(wn, a.m, ic, jc, a.gam));

@@ -43,8 +43,13 @@ def grid_geometry(solver):
 
 
 def relaxed_states(grid, seeds, t_ref, precision=64, batch=64, chunk=4000):
-    """Relax each seed's map for t_ref with the ensemble; yields
-    (seed, map, primitive SI state as a device tensor)."""
+    """Relax each seed's map for t_ref; yields (seed, map, primitive SI state
+    as a device tensor).  batch > 1: the batched ensemble, batch runs per
+    launch (small grids); batch = 1: one solver per map, stepping in graphs
+    (grids that fill the GPU on their own)."""
+    if batch == 1:
+        yield from _relaxed_single(grid, seeds, t_ref, precision, chunk)
+        return
     from .ensemble import Ensemble
     for b0 in range(0, len(seeds), batch):
         sub = seeds[b0:b0 + batch]
@@ -69,6 +74,30 @@ def relaxed_states(grid, seeds, t_ref, precision=64, batch=64, chunk=4000):
             if q not in failed:
                 yield s, m, run.get_state_device()
         e.close()
+
+
+def _relaxed_single(grid, seeds, t_ref, precision, chunk):
+    from .solver import Solver
+    s = Solver(grid, precision=precision)
+    t0 = time.perf_counter()
+    for q, seed in enumerate(seeds):
+        m = synth.relax_map(grid, seed)
+        s.set_maps(np.zeros(1), m[None])
+        s.init_radial()
+        ok = True
+        while True:
+            info = s.step(chunk, t_end=t_ref, raise_on_error=False)
+            if info["status"] != 0:
+                ok = False
+                break
+            if info["steps"] < chunk:
+                break
+        log(f"warmstart: map {q + 1}/{len(seeds)} (seed {seed}) relaxed to "
+            f"{t_ref / 86400:.1f} d, {time.perf_counter() - t0:.1f} s"
+            + ("" if ok else "; non-physical, dropped"))
+        if ok:
+            yield seed, m, s.get_state_device()
+    s.close()
 
 
 def build_dataset(net, grid, seeds, t_ref, rc, thc, precision=64, batch=64):
@@ -208,7 +237,12 @@ def main(argv=None):
                     help="reference relaxation length, slow-wind crossing times")
     ap.add_argument("--data-crossings", type=float, default=None,
                     help="relaxation length of the training targets (default: --crossings)")
-    ap.add_argument("--ens-batch", type=int, default=64, help="runs per ensemble launch")
+    ap.add_argument("--ens-batch", type=int, default=64,
+                    help="runs per ensemble launch; 1: one solver per map")
+    ap.add_argument("--train-seed0", type=int, default=TRAIN_SEED0,
+                    help="first training seed (disjoint chunks across calls)")
+    ap.add_argument("--init-weights", default=None,
+                    help="continue training from these weights")
     ap.add_argument("--data-precision", type=int, default=32)
     ap.add_argument("--out", default=None)
     ap.add_argument("--weights", default=None, help="evaluate these weights (skip training)")
@@ -226,8 +260,9 @@ def main(argv=None):
     lo = lo if args.phi_lo is None else args.phi_lo
     hi = hi if args.phi_hi is None else args.phi_hi
     dims = (g.nt, g.np_, g.nr, args.c1, args.c2, args.hidden, lo, hi)
-    if args.weights:
-        dims = tuple(int(v) for v in np.load(args.weights)["dims"])
+    src = args.weights or args.init_weights
+    if src:
+        dims = tuple(int(v) for v in np.load(src)["dims"])
         assert dims[:3] == (g.nt, g.np_, g.nr), "weights for another grid"
     net = WarmStartNet(*dims[:6], batch_max=8, phi_lo=dims[6], phi_hi=dims[7])
     p0 = init_params(*net.dims, seed=0)
@@ -236,11 +271,14 @@ def main(argv=None):
     probe.close()
     report = dict(grid=[g.nr, g.nt, g.np_], t_ref_days=t_ref / 86400, params=int(net.nparam),
                   dims=list(net.dims))
+    mean_t = None
     if args.weights:
-        p = np.load(args.weights)["params"]
-        mean_t = torch.from_numpy(np.load(args.weights)["mean_target"]).cuda()
+        w = np.load(args.weights)
+        p = w["params"]
+        if "mean_target" in w.files:
+            mean_t = torch.from_numpy(w["mean_target"]).cuda()
     else:
-        train_seeds = list(range(TRAIN_SEED0, TRAIN_SEED0 + args.train))
+        train_seeds = list(range(args.train_seed0, args.train_seed0 + args.train))
         t0 = time.perf_counter()
         t_data = t_ref if args.data_crossings is None else \
             args.data_crossings * relax.slow_crossing_time(g)
@@ -248,15 +286,17 @@ def main(argv=None):
         X, T, _ = build_dataset(net, g, train_seeds, t_data, rc, thc, args.data_precision,
                                 args.ens_batch)
         report["dataset_seconds"] = time.perf_counter() - t0
-        mean_t = T.mean(dim=0)
-        net.set_params(p0)
+        if not args.no_ablations:
+            mean_t = T.mean(dim=0)
+        net.set_params(np.load(args.init_weights)["params"] if args.init_weights else p0)
+        report["init_weights"] = args.init_weights
         report["train_samples"] = int(X.shape[0])
         hist, tsec = train(net, X, T, args.epochs, lr=args.lr)
         report.update(train_loss=hist, train_seconds=tsec)
         p = net.get_params()
         if args.out:
-            np.savez(args.out, params=p, mean_target=mean_t.cpu().numpy(),
-                     dims=np.array(net.dims))
+            extra = {} if mean_t is None else {"mean_target": mean_t.cpu().numpy()}
+            np.savez(args.out, params=p, dims=np.array(net.dims), **extra)
         del X, T
         torch.cuda.empty_cache()
     preds = {}
@@ -269,7 +309,12 @@ def main(argv=None):
     preds["warm"] = with_params(p)
     if not args.no_ablations:
         preds["untrained"] = with_params(p0)
-        preds["mean_target"] = lambda x: mean_t
+        if mean_t is not None:
+            preds["mean_target"] = lambda x: mean_t
+    if args.test == 0:
+        if args.report:
+            json.dump(report, open(args.report, "w"), indent=1, default=float)
+        return report
     test_seeds = list(range(TEST_SEED0, TEST_SEED0 + args.test))
     rows = evaluate(net, g, test_seeds, t_ref, preds)
     report["summary"] = summarise(rows, list(preds))
