@@ -125,6 +125,44 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R>& a, int kplanes, i
 #pragma unroll
   for (int v = 0; v < NV; ++v) fcar[v] = R(0);
 
+  // Stage 1 (PF): this thread's theta-halo item is the same (row, lane) of
+  // every plane, and the next plane's item is loaded while the current
+  // plane is processed.  Stage 2 has no registers to spare for it and
+  // loads each plane's halo after the plane barrier.
+  constexpr bool PF = STAGE == 1;
+  static_assert(4 * TR <= NT, "at most one theta-halo item per thread");
+  const bool hv = tid < 4 * TR;
+  const int hrow = tid / TR, hl = tid - hrow * TR;
+  const int hjj = hrow < 2 ? hrow - 2 : TT + hrow - 2;
+  const int hgi = i0 + hl - 2;
+  bool hflip;
+  const int hgj = mirror_row(j0 + hjj, nt, hflip);
+  const bool hghost = hgi < 0;  // below r_in: inner ghost primitives
+  const unsigned hoff = (unsigned)(hgj * nr + (hgi < 0 ? 0 : (hgi < nr ? hgi : nr - 1)));
+  auto halo_raw = [&](int k, R (&w)[NV]) {
+    if (hghost) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) w[v] = ldg(a.ghost + v * gplane, (unsigned)(k * nt + hgj));
+    } else {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) w[v] = ldg(a.uin + v * a.ncell, (unsigned)k * plane_cells + hoff);
+    }
+  };
+  auto halo_put = [&](const R (&raw)[NV]) {
+    R w[NV];
+    if (hghost) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) w[v] = raw[v];
+    } else {
+      cons2prim<R, true>(raw, w, a.gm1);
+    }
+    if (hflip) flip_theta(w);
+#pragma unroll
+    for (int v = 0; v < NV; ++v) sW[v][hjj + 2][hl] = w[v];
+  };
+  R hraw[NV];
+  if (PF && hv && k0 < kend) halo_raw(k0, hraw);
+
   double lam = 0.0, s1 = 0.0, s0 = 0.0;
   int bad = BAD_NONE;
 
@@ -145,23 +183,30 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R>& a, int kplanes, i
         for (int v = 0; v < NV; ++v) sW[v][tj + 2][ti] = wb[v];
       }
       // theta halo: rows -2, -1, TT, TT + 1 over all TR lanes
-      for (int h = tid; h < 4 * TR; h += NT) {
-        const int row = h / TR, l = h - row * TR;
-        const int jj = row < 2 ? row - 2 : TT + row - 2;
-        const int gi = i0 + l - 2;
-        bool flip;
-        const int gj = mirror_row(j0 + jj, nt, flip);
-        R w[NV];
-        if (gi < 0) {
-          const unsigned g = (unsigned)(k * nt + gj);
-#pragma unroll
-          for (int v = 0; v < NV; ++v) w[v] = ldg(a.ghost + v * gplane, g);
-        } else {
-          load_cons_prim<R, true>(a, kbase + (unsigned)(gj * nr + (gi < nr ? gi : nr - 1)), w);
+      if constexpr (PF) {
+        if (hv) {
+          halo_put(hraw);
+          if (k + 1 < kend) halo_raw(k + 1, hraw);  // in flight during this plane
         }
-        if (flip) flip_theta(w);
+      } else {
+        for (int h = tid; h < 4 * TR; h += NT) {
+          const int row = h / TR, l = h - row * TR;
+          const int jj = row < 2 ? row - 2 : TT + row - 2;
+          const int gi = i0 + l - 2;
+          bool flip;
+          const int gj = mirror_row(j0 + jj, nt, flip);
+          R w[NV];
+          if (gi < 0) {
+            const unsigned g = (unsigned)(k * nt + gj);
 #pragma unroll
-        for (int v = 0; v < NV; ++v) sW[v][jj + 2][l] = w[v];
+            for (int v = 0; v < NV; ++v) w[v] = ldg(a.ghost + v * gplane, g);
+          } else {
+            load_cons_prim<R, true>(a, kbase + (unsigned)(gj * nr + (gi < nr ? gi : nr - 1)), w);
+          }
+          if (flip) flip_theta(w);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) sW[v][jj + 2][l] = w[v];
+        }
       }
       __syncthreads();
       // r face i-1/2 and theta face j-1/2 at every lane (the update reads

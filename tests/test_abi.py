@@ -70,6 +70,7 @@ def test_workspace_size_and_validation(lib):
         (_grid(lib, n_r=0), p), (_grid(lib, r_out=0.05 * 1.5e11), p),
         (_grid(lib, th_min=0.0), p), (_grid(lib, th_max=3.5), p),
         (_grid(lib, n_r=2000, n_theta=2000, n_phi=1000), p),  # > 2^31 cells
+        (_grid(lib, n_r=1024, n_theta=1024, n_phi=512), p),  # 2^29 cells: 4 GiB per variable
         (_grid(lib, max_maps=0), p), (_grid(lib, max_probes=2, max_traj_pts=1), p),
         (g, _phys(lib, gamma=1.0)), (g, _phys(lib, cfl=0.0)), (g, _phys(lib, cfl=1.5)),
         (g, _phys(lib, flux=7)), (g, _phys(lib, limiter=3)), (g, _phys(lib, limiter=4)), (g, _phys(lib, precision=16)),
@@ -79,6 +80,9 @@ def test_workspace_size_and_validation(lib):
         rc = L.icr_workspace_bytes(ctypes.byref(gg), ctypes.byref(pp), ctypes.byref(n))
         assert rc == lib.ICR_ERR_ARG
         assert len(L.icr_last_error()) > 0
+    # the largest grid the kernels address with 32-bit offsets is accepted
+    big = _grid(lib, n_r=1024, n_theta=1024, n_phi=511)
+    assert L.icr_workspace_bytes(ctypes.byref(big), ctypes.byref(p), ctypes.byref(n)) == 0
 
 
 def test_units_match_the_oracle(lib):
