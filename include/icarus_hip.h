@@ -278,8 +278,9 @@ int icr_boundary_at(icr_solver *s, double t_s, double *out);
  * (2), 1 = one thread per cell with on-the-fly neighbour primitives, 2 =
  * face-once kernel (LDS tile with halo in r/theta, registers along phi).
  * tile_r: lanes along r per block (variant 1: 64, 128, 256; variant 2: 32,
- * 64; 0 = 64; a solver with the passive tracer keeps 64 for variant 2; a
- * WENO5 solver always runs variant 1);
+ * 64, of which the first two and the last two hold the r halo, so a block
+ * updates tile_r - 4 cells along r; 0 = 64; a solver with the passive
+ * tracer keeps 64 for variant 2; a WENO5 solver always runs variant 1);
  * 256 threads per block.  planes: phi planes per block of
  * variant 2 (1..n_phi, 0 = 8).  use_graphs: 1 replays steps from captured
  * HIP graphs.  All tiles and plane counts of one variant give bit-identical

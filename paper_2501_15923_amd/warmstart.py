@@ -241,6 +241,8 @@ def main(argv=None):
                     help="runs per ensemble launch; 1: one solver per map")
     ap.add_argument("--train-seed0", type=int, default=TRAIN_SEED0,
                     help="first training seed (disjoint chunks across calls)")
+    ap.add_argument("--test-seed0", type=int, default=TEST_SEED0,
+                    help="first held-out seed (evaluation split across calls)")
     ap.add_argument("--init-weights", default=None,
                     help="continue training from these weights")
     ap.add_argument("--data-precision", type=int, default=32)
@@ -315,7 +317,7 @@ def main(argv=None):
         if args.report:
             json.dump(report, open(args.report, "w"), indent=1, default=float)
         return report
-    test_seeds = list(range(TEST_SEED0, TEST_SEED0 + args.test))
+    test_seeds = list(range(args.test_seed0, args.test_seed0 + args.test))
     rows = evaluate(net, g, test_seeds, t_ref, preds)
     report["summary"] = summarise(rows, list(preds))
     report["rows"] = rows
