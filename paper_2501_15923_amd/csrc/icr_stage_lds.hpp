@@ -236,18 +236,14 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R>& a, int kplanes, i
         }
       }
     }
-    // The own cell's conserved values for the update (and, in stage 2, those
-    // of U^n) are loaded here, before the phi face and the barrier, so that
-    // their latency overlaps that work instead of stalling the update.
-    R uc[NV], up[NV];
-    if (body && valid) {
+    // Stage 2: the own cell's U^n for the RK combine is loaded here, before
+    // the phi face and the barrier, so that its latency overlaps that work
+    // instead of stalling the update.
+    R up[NV];
+    if (STAGE == 2 && body && valid) {
       const unsigned c = kbase + colbase;
 #pragma unroll
-      for (int v = 0; v < NV; ++v) uc[v] = ldg(a.uin + v * a.ncell, c);
-      if (STAGE == 2) {
-#pragma unroll
-        for (int v = 0; v < NV; ++v) up[v] = ldg(a.un + v * a.ncell, c);
-      }
+      for (int v = 0; v < NV; ++v) up[v] = ldg(a.un + v * a.ncell, c);
     }
     // phi face k+1/2 from the register ring (and the next plane's load)
     R fhi[NV];
@@ -280,6 +276,10 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R>& a, int kplanes, i
           L[v] -= fph * (fhi[v] - fcar[v]);
         }
         add_sources<R>(wa, a.m, ic, jc, a.omega, a.gravity, a.corot, L);
+        // the stage's own conserved state, rebuilt from the ring's primitives
+        // (equal to the stored values up to rounding; no reload)
+        R uc[NV];
+        prim2cons<R>(wa, uc, a.igm1);
         const R dt = (R)a.clock->dt;
         const unsigned c = kbase + colbase;
         if constexpr (FM) {  // passive tracer on: keep this stage's mass fluxes
