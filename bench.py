@@ -24,6 +24,9 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, GB/s
+# VALU issue ceiling: 256 CUs x 4 SIMDs x 16 lanes per clock x 2.4 GHz (a wave64 VALU
+# instruction occupies a SIMD for 4 clocks; the same rate as the 78.6 TFLOP/s FP64 FMA peak)
+VALU_PEAK_LANE_INSTR = 256 * 4 * 16 * 2.4e9
 FP64_BYTES_STAGE = (128, 192)   # algorithmic bytes per cell: stage 1, stage 2 (FP64)
 
 
@@ -46,9 +49,11 @@ def parse():
                     help="HBM traffic per stage-2 launch measured with rocprofv3 counters")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a device-to-device copy of known size (counter calibration)")
-    ap.add_argument("--ingest-counters", nargs=4, default=None,
-                    metavar=("FETCH_DIR", "WRITE_DIR", "COPY_FETCH_DIR", "COPY_WRITE_DIR"),
-                    help="write the --traffic file from four rocprofv3 --pmc output folders")
+    ap.add_argument("--ingest-counters", nargs="+", default=None,
+                    metavar="DIR",
+                    help="write the --traffic file from rocprofv3 --pmc output folders: "
+                         "FETCH_SIZE and WRITE_SIZE of this bench, of --copy-calibration, "
+                         "then optionally one with SQ_INSTS_VALU of this bench")
     ap.add_argument("--workload", default="prod",
                     choices=("prod", "ensemble", "relax", "jupiter"),
                     help="prod: 600x60x120 dynamic run (the headline line); ensemble: 64 "
@@ -293,7 +298,10 @@ def copy_calibration():
 def ingest_counters(dirs, precision, out_path):
     """Turn four rocprofv3 --pmc runs (FETCH_SIZE and WRITE_SIZE of this
     bench, then of --copy-calibration) into HBM bytes per stage-2 launch.
-    Each counter is scaled by what it reads for the 2 GiB copy."""
+    Each counter is scaled by what it reads for the 2 GiB copy.  A fifth run
+    with SQ_INSTS_VALU adds the stage-2 VALU wave-instructions per launch."""
+    if len(dirs) not in (4, 5):
+        raise SystemExit("--ingest-counters takes 4 or 5 folders")
     import csv
     import glob
 
@@ -314,8 +322,9 @@ def ingest_counters(dirs, precision, out_path):
         args = name.split("k_stage_lds<", 1)[1].split(">", 1)[0].split(",")
         return int(args[5]) if len(args) > 5 else None
 
-    def stage2_mean(d):
-        v = [float(r["Counter_Value"]) for r in rows(d) if stage_of(r["Kernel_Name"]) == 2]
+    def stage2_mean(d, counter=None):
+        v = [float(r["Counter_Value"]) for r in rows(d) if stage_of(r["Kernel_Name"]) == 2
+             and (counter is None or r["Counter_Name"] == counter)]
         assert v, f"no stage-2 dispatches in {d}"
         return sum(v) / len(v), len(v)
 
@@ -326,6 +335,8 @@ def ingest_counters(dirs, precision, out_path):
            "fetch_bytes": fetch * sf, "write_bytes": write * sw,
            "bytes_per_launch": fetch * sf + write * sw,
            "fetch_scale": sf, "write_scale": sw, "dispatches": [n_f, n_w]}
+    if len(dirs) == 5:
+        rec["valu_wave_instr_per_launch"], _ = stage2_mean(dirs[4], "SQ_INSTS_VALU")
     json.dump(rec, open(out_path, "w"), indent=1)
     print(json.dumps(rec), flush=True)
 
@@ -413,11 +424,20 @@ def main():
     bytes2 = bpc[1] * g.cells
     achieved = bytes2 / (kms[2] * 1e-3) / 1e9
     traffic = None
+    valu = None
     if os.path.exists(args.traffic):
         try:
             tr = json.load(open(args.traffic))
             if tr.get("precision") == args.precision and tr.get("kernel_rev") == kernel_rev():
                 traffic = tr.get("bytes_per_launch")
+                vi = tr.get("valu_wave_instr_per_launch")
+                if vi:
+                    lane = 64 * vi / (kms[2] * 1e-3)
+                    valu = {"achieved": round(lane / 1e12, 2), "peak": VALU_PEAK_LANE_INSTR / 1e12,
+                            "unit": "T lane-instr/s", "frac": round(lane / VALU_PEAK_LANE_INSTR, 4),
+                            "instr_per_cell": round(64 * vi / g.cells),
+                            "note": "all VALU instructions of the stage-2 kernel (counted once "
+                                    "with rocprofv3) over its live duration"}
         except Exception:
             traffic = None
     roof = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
@@ -425,6 +445,8 @@ def main():
             "kernel": "stage 2 (fused reconstruct/flux/update + CFL/residual reduction)",
             "stage1_GBs": round(bpc[0] * g.cells / (kms[1] * 1e-3) / 1e9, 1),
             "kernel_ms": [round(float(x), 4) for x in kms]}
+    if valu is not None:
+        roof["valu_issue"] = valu
     out = {
         "metric": "MHD cell-updates/s & % HBM roofline; relax wall-time plain vs warm-start",
         "value": value, "unit": "cell-updates/s", "n_gpus": 1, "steps": args.steps,
