@@ -116,6 +116,25 @@ def build_dataset(net, grid, seeds, t_ref, rc, thc, precision=64, batch=64):
     return X[:q], T[:q], M[:q]
 
 
+def scale_output(params, dims, s):
+    """Scale the last layer's weights and biases of output variable v (the
+    output index is r * 8 + v) by s[v].  Training on targets scaled the same
+    way weights the squared error of variable v by s[v]^2 (the last layer is
+    linear); dividing by s afterwards returns the usual output."""
+    nt, nph, nr, c1, c2, hidden, lo, hi = (int(d) for d in dims)
+    k1 = 3 * (hi - lo + 1) * 8
+    no = 8 * nr
+    p = np.array(params, dtype=np.float32, copy=True)
+    off = k1 * c1 + c1 + 9 * c1 * c2 + c2 + c2 * hidden + hidden
+    W4 = p[off:off + hidden * no].reshape(hidden, no)
+    b4 = p[off + hidden * no:off + hidden * no + no]
+    col = np.tile(np.asarray(s, dtype=np.float32), nr)
+    W4 *= col[None, :]
+    b4 *= col
+    assert off + hidden * no + no == p.size
+    return p
+
+
 def default_window(grid, v_slow=350e3):
     """First-layer longitude offsets reaching the footpoint of slow wind at the
     outer radius: Omega (r_out - r_in) / v_slow, in cells, plus one; two
@@ -249,6 +268,9 @@ def main(argv=None):
     ap.add_argument("--out", default=None)
     ap.add_argument("--weights", default=None, help="evaluate these weights (skip training)")
     ap.add_argument("--report", default=None)
+    ap.add_argument("--rho-weight", type=float, default=1.0,
+                    help="loss weight of the density output (targets and the output layer "
+                         "scaled by its square root while training)")
     ap.add_argument("--no-ablations", action="store_true",
                     help="evaluate the trained network only (no untrained / mean-state starts)")
     args = ap.parse_args(argv)
@@ -290,12 +312,21 @@ def main(argv=None):
         report["dataset_seconds"] = time.perf_counter() - t0
         if not args.no_ablations:
             mean_t = T.mean(dim=0)
-        net.set_params(np.load(args.init_weights)["params"] if args.init_weights else p0)
+        p_init = np.load(args.init_weights)["params"] if args.init_weights else p0
+        osc = np.ones(8)
+        osc[0] = math.sqrt(args.rho_weight)
+        if args.rho_weight != 1.0:
+            T[..., 0::8] *= float(osc[0])
+            p_init = scale_output(p_init, net.dims, osc)
+        net.set_params(p_init)
         report["init_weights"] = args.init_weights
+        report["rho_weight"] = args.rho_weight
         report["train_samples"] = int(X.shape[0])
         hist, tsec = train(net, X, T, args.epochs, lr=args.lr)
         report.update(train_loss=hist, train_seconds=tsec)
         p = net.get_params()
+        if args.rho_weight != 1.0:
+            p = scale_output(p, net.dims, 1.0 / osc)
         if args.out:
             extra = {} if mean_t is None else {"mean_target": mean_t.cpu().numpy()}
             np.savez(args.out, params=p, dims=np.array(net.dims), **extra)
