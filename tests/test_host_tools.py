@@ -1,0 +1,68 @@
+"""CPU checks of host-side tools: the output-layer scaling that weights the
+warm-start loss per variable, and the ingest of rocprofv3 counter files into
+the traffic record that bench.py reports."""
+import csv
+import json
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+
+def test_scale_output_round_trip_and_layout():
+    from paper_2501_15923_amd.nn import init_params
+    from paper_2501_15923_amd.warmstart import scale_output
+    dims = (6, 8, 5, 4, 3, 7, -1, 2)
+    p = init_params(*dims[:6], phi_lo=dims[6], phi_hi=dims[7], seed=1)
+    p[-40:] += 0.25  # non-zero output biases
+    s = np.ones(8)
+    s[0], s[3] = 2.0, 0.5
+    q = scale_output(p, dims, s)
+    assert np.array_equal(scale_output(q, dims, 1.0 / s), p)  # powers of two: exact
+    k1 = 3 * (dims[7] - dims[6] + 1) * 8
+    c1, c2, h, no = dims[3], dims[4], dims[5], 8 * dims[2]
+    off = k1 * c1 + c1 + 9 * c1 * c2 + c2 + c2 * h + h
+    W, Wq = p[off:off + h * no].reshape(h, no), q[off:off + h * no].reshape(h, no)
+    b, bq = p[off + h * no:], q[off + h * no:]
+    for v in range(8):  # output index r * 8 + v
+        assert np.allclose(Wq[:, v::8], s[v] * W[:, v::8])
+        assert np.allclose(bq[v::8], s[v] * b[v::8])
+    assert np.array_equal(q[:off], p[:off])  # encoder and first decoder layer untouched
+
+
+def _write_counters(d, rows):
+    os.makedirs(d, exist_ok=True)
+    with open(os.path.join(d, "p_counter_collection.csv"), "w", newline="") as f:
+        w = csv.DictWriter(f, fieldnames=["Kernel_Name", "Counter_Name", "Counter_Value"])
+        w.writeheader()
+        for r in rows:
+            w.writerow(r)
+
+
+def test_ingest_counters_scales_by_the_copy_and_adds_valu(tmp_path):
+    import bench
+    k2 = "void icr::k_stage_lds<double, 64, 4, 0, 0, 2, false>(icr::StageArgs<double>, int)"
+    k1 = "void icr::k_stage_lds<double, 64, 4, 0, 0, 1, false>(icr::StageArgs<double>, int)"
+    cp = "__amd_rocclr_copyBuffer"
+    d = [str(tmp_path / n) for n in ("f", "w", "cf", "cw", "sq")]
+    _write_counters(d[0], [dict(Kernel_Name=k2, Counter_Name="FETCH_SIZE", Counter_Value=v)
+                           for v in (1000.0, 1200.0)] +
+                    [dict(Kernel_Name=k1, Counter_Name="FETCH_SIZE", Counter_Value=9e9)])
+    _write_counters(d[1], [dict(Kernel_Name=k2, Counter_Name="WRITE_SIZE", Counter_Value=500.0)])
+    # the copy of 2 GiB reads 2^20 counted units for FETCH and 2^21 for WRITE
+    _write_counters(d[2], [dict(Kernel_Name=cp, Counter_Name="FETCH_SIZE", Counter_Value=2**20)])
+    _write_counters(d[3], [dict(Kernel_Name=cp, Counter_Name="WRITE_SIZE", Counter_Value=2**21)])
+    _write_counters(d[4], [dict(Kernel_Name=k2, Counter_Name="SQ_INSTS_VALU", Counter_Value=64.0),
+                           dict(Kernel_Name=k2, Counter_Name="SQ_WAVES", Counter_Value=1.0)])
+    out = str(tmp_path / "t.json")
+    bench.ingest_counters(d[:4], 64, out)
+    rec = json.load(open(out))
+    assert rec["fetch_bytes"] == 1100.0 * 2048 and rec["write_bytes"] == 500.0 * 1024
+    assert rec["bytes_per_launch"] == rec["fetch_bytes"] + rec["write_bytes"]
+    assert rec["kernel_rev"] == bench.kernel_rev() and "valu_wave_instr_per_launch" not in rec
+    bench.ingest_counters(d, 64, out)
+    assert json.load(open(out))["valu_wave_instr_per_launch"] == 64.0
