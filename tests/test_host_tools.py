@@ -1,6 +1,8 @@
 """CPU checks of host-side tools: the output-layer scaling that weights the
-warm-start loss per variable, and the ingest of rocprofv3 counter files into
-the traffic record that bench.py reports."""
+warm-start loss per variable, the ingest of rocprofv3 counter files into the
+traffic record that bench.py reports, the relaxation criteria (first record
+with residual < tol and both 1 AU shell errors within tol), the warm-start
+longitude window and the evaluation summary."""
 import csv
 import json
 import os
@@ -66,3 +68,55 @@ def test_ingest_counters_scales_by_the_copy_and_adds_valu(tmp_path):
     assert rec["kernel_rev"] == bench.kernel_rev() and "valu_wave_instr_per_launch" not in rec
     bench.ingest_counters(d, 64, out)
     assert json.load(open(out))["valu_wave_instr_per_launch"] == 64.0
+
+
+def test_relaxation_criteria_pick_the_first_record_meeting_both():
+    from paper_2501_15923_amd import relax
+    # (steps, wall, residual, err_rho, err_vr)
+    rec = [(50, 0.1, 3e-4, 0.50, 0.10), (100, 0.2, 9e-5, 0.030, 0.01),
+           (150, 0.3, 2e-4, 0.015, 0.01), (200, 0.4, 8e-5, 0.019, 0.02),
+           (250, 0.5, 5e-5, 0.010, 0.005)]
+    out = relax.first_relaxed(rec, 1e-4, 0.02)
+    assert out["converged"] and out["steps"] == 200 and out["wall"] == 0.4
+    none = relax.first_relaxed(rec[:3], 1e-4, 0.02)
+    assert not none["converged"] and none["steps"] == 150
+
+
+def test_shell_errors_and_crossing_time():
+    from paper_2501_15923_amd import relax, synth
+    ref = np.stack([np.full((4, 5), 2.0), np.full((4, 5), 400e3)])
+    sh = ref.copy()
+    sh[0] *= 1.03
+    sh[1, 0, 0] += 4e3  # one of 20 points off by 1 %
+    er, ev = relax.shell_errors(sh, ref)
+    assert abs(er - 0.03) < 1e-12
+    assert abs(ev - 0.01 / np.sqrt(20)) < 1e-12
+    g = synth.Grid(150, 30, 60)
+    assert abs(relax.slow_crossing_time(g) - 1.9 * synth.AU / 350e3) < 1e-6 * 1.9 * synth.AU / 350e3
+
+
+def test_default_window_reaches_the_slow_wind_footpoint():
+    import math
+
+    from paper_2501_15923_amd import synth
+    from paper_2501_15923_amd.warmstart import default_window
+    for g in (synth.Grid(150, 30, 60), synth.Grid(600, 60, 120)):
+        lo, hi = default_window(g)
+        dph = 2 * math.pi / g.np_
+        lag = synth.OMEGA_SUN * (g.r_out - g.r_in) / 350e3  # longitude lag at r_out, rad
+        assert lo == -2 and (hi - 1) * dph >= lag > (hi - 2) * dph
+    assert default_window(synth.Grid(150, 30, 60)) == (-2, 24)
+    assert default_window(synth.Grid(600, 60, 120)) == (-2, 46)
+
+
+def test_summarise_ratios_over_converged_runs():
+    from paper_2501_15923_amd.warmstart import summarise
+
+    def row(ps, pw, ws, ww, conv=True):
+        return dict(plain=dict(converged=True, steps=ps, wall=pw),
+                    warm=dict(converged=conv, steps=ws, wall=ww, err_rho=0.019, err_vr=0.002))
+    rows = [row(1000, 1.0, 300, 0.3), row(1200, 1.2, 600, 0.6), row(900, 0.9, 900, 0.9, False)]
+    s = summarise(rows, ["warm"])["warm"]
+    assert s["converged"] == 2 and s["of"] == 3
+    assert abs(s["wall_ratio_median"] - 0.4) < 1e-12 and abs(s["wall_ratio_mean"] - 0.4) < 1e-12
+    assert s["steps_median"] == 450.0 and s["plain_steps_median"] == 1100.0
