@@ -27,7 +27,10 @@
  *   - Host inputs are copied; the caller keeps ownership of every buffer it
  *     passes.  Device memory for the solver comes from the caller: query
  *     icr_workspace_bytes(), allocate that many bytes of device memory
- *     (256-byte aligned) and keep it alive until icr_destroy().
+ *     (256-byte aligned) and keep it alive until icr_destroy().  No call
+ *     allocates device memory: host <-> device copies of states, tracers
+ *     and divergences go through a staging region of that workspace in
+ *     chunks of 65536 cells.
  *   - API quantities are SI: metres, seconds, kg/m^3, m/s, Pa, tesla,
  *     radians.  theta is colatitude, phi longitude in the co-rotating frame.
  *   - Primitive channel order (maps and states):
@@ -67,6 +70,15 @@ enum { ICR_FLUX_TVDLF = 0, ICR_FLUX_HLL = 1, ICR_FLUX_HLLD = 2 };
  * rho or p <= 0 falls back to its cell value). */
 enum { ICR_LIM_MINMOD = 0, ICR_LIM_MC = 1, ICR_LIM_WENO5 = 2 };
 enum { ICR_PREC_F64 = 64, ICR_PREC_F32 = 32 };
+/* Transverse quantities (v_theta, v_phi, B_theta, B_phi) at the inner
+ * boundary (Sect. 2.1).  MAP: every ghost layer takes the map's values
+ * (after time interpolation and the cone-CME overwrite), like rho, v_r, p
+ * and B_r.  ASYMM: the paper's default for the quantities a coronal model
+ * does not provide; ghost layer g takes minus the primitive of active cell
+ * g-1 (the mirror image about r_in), so they vanish on the boundary
+ * surface, while rho, v_r, p and B_r still come from the map.  ASYMM needs
+ * n_r >= the ghost width (2; 3 for WENO5). */
+enum { ICR_BCT_MAP = 0, ICR_BCT_ASYMM = 1 };
 
 /* State kinds for icr_set_state / icr_get_state. */
 enum {
@@ -106,6 +118,7 @@ typedef struct {
   int corotation;            /* 1: centrifugal + Coriolis sources        */
   int tracer;                /* 1: carry the passive CME tracer (single
                                 solvers only; ensembles reject it)       */
+  int bc_transverse;         /* ICR_BCT_MAP or ICR_BCT_ASYMM             */
 } icr_phys;
 
 /* Clock: time [s] since the map time origin, completed RK2 steps, the dt of
@@ -293,6 +306,14 @@ int icr_set_launch(icr_solver *s, int variant, int tile_r, int planes,
  * of the boundary driver, stage 1, stage 2 and the finalize kernel (clock,
  * dt and probe record).  Same results as icr_step. */
 int icr_profile_steps(icr_solver *s, int n_steps, double *avg_ms);
+
+/* Accuracy diagnostic of the FP64 reciprocal and square root the face-once
+ * stage kernels use instead of division and sqrt (hardware estimate refined
+ * by two Newton-Raphson steps, and by two Goldschmidt iterations plus a
+ * residual correction): rcp[q] = 1/x[q], sq[q] = sqrt(x[q]) for n device
+ * doubles (positive normal x).  All pointers device memory; synchronises
+ * the stream. */
+int icr_fast_math(const double *x, long long n, double *rcp, double *sq, void *hip_stream);
 
 /* ------------------------------------------------------------------------
  * Batched ensemble (not in the paper; many independent runs on one GPU).

@@ -456,6 +456,11 @@ void *orc_create(const int *ip, const double *dp) {
   c->slab_bcx = ip[10];
   c->tracer = ip[11] && ip[3] == GEOM_SPH;
   c->ng = c->limiter == LIM_WENO5 ? 3 : 2;
+  /* asymm mirrors active cell g-1 into ghost layer g: needs ng cells in r */
+  if (c->bc_transverse == BCT_ASYMM && c->nr < c->ng) {
+    free(c);
+    return 0;
+  }
   c->gr = c->nr + 2 * c->ng;
   c->gt = c->nt + 2 * c->ng;
   c->gp = c->np + 2 * c->ng;

@@ -12,6 +12,7 @@ ICR_OK, ICR_ERR_ARG, ICR_ERR_STATE, ICR_ERR_NONPHYSICAL, ICR_ERR_HIP, ICR_ERR_UN
 FLUX_TVDLF, FLUX_HLL, FLUX_HLLD = 0, 1, 2
 LIM_MINMOD, LIM_MC, LIM_WENO5 = 0, 1, 2
 PREC_F64, PREC_F32 = 64, 32
+BCT_MAP, BCT_ASYMM = 0, 1
 STATE_PRIM_SI, STATE_CONS_CODE = 0, 1
 
 
@@ -27,7 +28,8 @@ class IcrGrid(ctypes.Structure):
 class IcrPhys(ctypes.Structure):
     _fields_ = [("gamma", ctypes.c_double), ("omega", ctypes.c_double), ("cfl", ctypes.c_double),
                 ("flux", ctypes.c_int), ("limiter", ctypes.c_int), ("precision", ctypes.c_int),
-                ("gravity", ctypes.c_int), ("corotation", ctypes.c_int), ("tracer", ctypes.c_int)]
+                ("gravity", ctypes.c_int), ("corotation", ctypes.c_int), ("tracer", ctypes.c_int),
+                ("bc_transverse", ctypes.c_int)]
 
 
 class IcrClock(ctypes.Structure):
@@ -84,6 +86,7 @@ SIGNATURES = {
     "icr_boundary_at": (I, [P, ctypes.c_double, D]),
     "icr_set_launch": (I, [P, I, I, I, I]),
     "icr_profile_steps": (I, [P, I, D]),
+    "icr_fast_math": (I, [D, ctypes.c_longlong, D, D, P]),
     "icr_ens_workspace_bytes": (I, [I, ctypes.POINTER(IcrGrid), ctypes.POINTER(IcrPhys),
                                     ctypes.POINTER(ctypes.c_size_t)]),
     "icr_ens_create": (I, [I, ctypes.POINTER(IcrGrid), ctypes.POINTER(IcrPhys), P,

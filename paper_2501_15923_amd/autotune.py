@@ -61,13 +61,13 @@ def _time(fn, reps):
 def solver_candidates(g):
     out = []
     for tr in (64, 32):
-        for planes in (2, 4, 6, 8, 12, 16):
+        for planes in (2, 4, 5, 6, 8, 10, 12, 15, 16):
             if planes <= g.np_:
                 out.append((tr, planes))
     return out
 
 
-def tune_solver(g, precision=64, flux=0, limiter=0, steps=6, cache=DEFAULT_CACHE):
+def tune_solver(g, precision=64, flux=0, limiter=0, steps=32, cache=DEFAULT_CACHE):
     """Best (tile_r, planes) for one grid; cached."""
     key = f"solver|{_device_name()}|{precision}|{flux}{limiter}|{g.nr}x{g.nt}x{g.np_}"
     db = _load(cache) if cache else {}
@@ -77,10 +77,11 @@ def tune_solver(g, precision=64, flux=0, limiter=0, steps=6, cache=DEFAULT_CACHE
     s = Solver(g, precision=precision, flux=flux, limiter=limiter)
     s.set_maps(*_uniform_inputs(g))
     s.init_radial()
+    s.step(4 * steps)  # clocks up before the first candidate
     timings = {}
     for tr, planes in solver_candidates(g):
         s.set_launch(2, tr, planes, 1)
-        s.step(2)
+        s.step(16)
         timings[f"{tr}x{planes}"] = _time(s.step, steps)
     s.close()
     best = min(timings, key=timings.get)

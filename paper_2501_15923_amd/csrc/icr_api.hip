@@ -70,11 +70,16 @@ struct Units {
 };
 
 constexpr int CHUNK = 16;  // steps per captured graph (even: parity kept)
+// Host <-> device copies of states, tracers and divergences go through a
+// staging region of the workspace in chunks of this many cells (8 doubles
+// each): no call after creation allocates device memory.
+constexpr long long STAGE_CELLS = 65536;
 
 size_t align_up(size_t x) { return (x + 255) & ~size_t(255); }
 
 struct Layout {
-  size_t u[3], g[2], m64, mr, maps, tau, cme, traj, plog, pout, clock, partials, bout, total;
+  size_t u[3], g[2], m64, mr, maps, tau, cme, traj, plog, pout, clock, partials, stage, total;
+  long long stage_cells;  // cells per host-transfer chunk
   size_t t[3], fm, frout, ftend, tg[2];  // passive tracer (0 when off)
   long long max_blocks;
 };
@@ -116,7 +121,11 @@ Layout make_layout(const icr_grid& g, const icr_phys& p) {
   L.pout = take(sizeof(double) * 12 * (size_t)(g.max_probes > 0 ? g.max_probes : 1));
   L.clock = take(sizeof(DevClock));
   L.partials = take(sizeof(double) * 4 * (size_t)L.max_blocks);
-  L.bout = take(sizeof(double) * NV * plane);
+  // staging: the boundary / shell outputs ([8][nt][np] doubles at most) and
+  // host-transfer chunks of stage_cells cells x 8 doubles
+  L.stage_cells = (long long)ncell < STAGE_CELLS ? (long long)ncell : STAGE_CELLS;
+  const size_t sb = (size_t)L.stage_cells > plane ? (size_t)L.stage_cells : plane;
+  L.stage = take(sizeof(double) * NV * sb);
   if (p.tracer) {
     for (int q = 0; q < 3; ++q) L.t[q] = take(ncell * rs);
     L.fm = take(3 * ncell * rs);
@@ -156,6 +165,11 @@ int validate(const icr_grid* g, const icr_phys* p) {
   if (p->precision != ICR_PREC_F64 && p->precision != ICR_PREC_F32)
     return fail(ICR_ERR_ARG, "precision must be 64 or 32");
   if (p->tracer != 0 && p->tracer != 1) return fail(ICR_ERR_ARG, "tracer must be 0 or 1");
+  if (p->bc_transverse != ICR_BCT_MAP && p->bc_transverse != ICR_BCT_ASYMM)
+    return fail(ICR_ERR_ARG, "unknown bc_transverse %d", p->bc_transverse);
+  const int ghost_width = p->limiter == ICR_LIM_WENO5 ? 3 : 2;
+  if (p->bc_transverse == ICR_BCT_ASYMM && g->n_r < ghost_width)
+    return fail(ICR_ERR_ARG, "asymm needs n_r >= %d (got %d)", ghost_width, g->n_r);
   return ICR_OK;
 }
 
@@ -179,6 +193,10 @@ struct icr_solver {
   int tile_r, variant, use_graphs, planes;
   hipGraphExec_t g_chunk[2], g_one[2];
   bool graphs_ok;
+  int dev;                  // HIP device the solver was created on
+  double* part_override;    // non-null: stage-2 partials go here instead
+
+  double* partials() { return part_override ? part_override : (double*)(ws + L.partials); }
 
   void* u(int q) { return ws + L.u[q]; }
   bool trc() const { return p.tracer != 0; }
@@ -229,7 +247,7 @@ struct icr_solver {
     a.ghost = (const R*)ghost(gh);
     a.m = metric_view<R>((const R*)mr(), g.n_r, g.n_theta, (g.th_max - g.th_min) / g.n_theta);
     a.clock = clock();
-    a.partials = (double*)(ws + L.partials);
+    a.partials = partials();
     a.nr = g.n_r;
     a.nt = g.n_theta;
     a.np = g.n_phi;
@@ -241,6 +259,7 @@ struct icr_solver {
     a.cfl = p.cfl;
     a.gravity = p.gravity ? 1 : 0;
     a.corot = p.corotation ? 1 : 0;
+    a.asymm = p.bc_transverse == ICR_BCT_ASYMM ? 1 : 0;
     a.fmass = trc() ? (R*)(ws + L.fm) : nullptr;
     a.fmass_rout = trc() ? (R*)(ws + L.frout) : nullptr;
     a.fmass_tend = trc() ? (R*)(ws + L.ftend) : nullptr;
@@ -305,8 +324,8 @@ struct icr_solver {
       launch_stage_lds<R>(a2, 2, p.flux, p.limiter, tile_r, planes, st);
     if (trc()) launch_tracer<R>(tracer_args<R>(2, 2, from, to, 1), 2, st);
     if (ev) (void)hipEventRecord(ev[3], st);
-    launch_finalize<R>(clock(), (const double*)(ws + L.partials), stage_blocks(), p.cfl, 1,
-                       logging() ? 1 : 0, probe_args(), u(to), (double*)(ws + L.plog), st);
+    launch_finalize<R>(clock(), partials(), stage_blocks(), p.cfl, 1, logging() ? 1 : 0,
+                       probe_args(), u(to), (double*)(ws + L.plog), st);
   }
 
   // One RK2 step from state buffer `from` into `from ^ 1`: boundary driver,
@@ -329,7 +348,7 @@ struct icr_solver {
   void enqueue_cfl(hipStream_t st) {
     const dim3 gr(((unsigned)g.n_r + 63) / 64, ((unsigned)g.n_theta + 3) / 4, g.n_phi);
     const int nb = (int)(gr.x * gr.y * gr.z);
-    const double* part = (const double*)(ws + L.partials);
+    const double* part = partials();
     if (f32) {
       launch_cfl<float>(stage_args<float>(cur, cur, cur, 0), gr, dim3(64, 4), st);
       launch_finalize<float>(clock(), part, nb, p.cfl, 0, 0, probe_args(), u(cur), nullptr, st);
@@ -361,6 +380,10 @@ struct icr_solver {
     (void)hipGraphDestroy(graph);
     if (e != hipSuccess)
       return fail(ICR_ERR_HIP, "hipGraphInstantiate failed: %s", hipGetErrorString(e));
+    // upload now, so that the first replay does not carry the upload
+    e = hipGraphUpload(*out, stream);
+    if (e != hipSuccess)
+      return fail(ICR_ERR_HIP, "hipGraphUpload failed: %s", hipGetErrorString(e));
     return ICR_OK;
   }
 
@@ -442,7 +465,13 @@ int icr_create(const icr_grid* g, const icr_phys* p, void* ws, size_t ws_bytes, 
   s->planes = 8;
   s->use_graphs = 1;
   s->graphs_ok = false;
-  hipError_t e = hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking);
+  s->part_override = nullptr;
+  hipError_t e = hipGetDevice(&s->dev);
+  if (e != hipSuccess) {
+    delete s;
+    return fail(ICR_ERR_HIP, "hipGetDevice failed: %s", hipGetErrorString(e));
+  }
+  e = hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking);
   if (e != hipSuccess) {
     delete s;
     return fail(ICR_ERR_HIP, "hipStreamCreate failed: %s", hipGetErrorString(e));
@@ -672,26 +701,31 @@ int icr_set_state(icr_solver* s, const double* data, int kind, int on_device) {
   if (kind != ICR_STATE_PRIM_SI && kind != ICR_STATE_CONS_CODE)
     return fail(ICR_ERR_ARG, "unknown state kind %d", kind);
   const long long n = s->ncell();
-  const size_t bytes = sizeof(double) * NV * (size_t)n;
-  const double* src = data;
-  double* tmp = nullptr;
-  if (!on_device) {
-    HIP_TRY(hipMalloc(&tmp, bytes));
-    hipError_t e = hipMemcpyAsync(tmp, data, bytes, hipMemcpyHostToDevice, s->stream);
-    if (e != hipSuccess) {
-      (void)hipFree(tmp);
-      return fail(ICR_ERR_HIP, "copy of the state failed: %s", hipGetErrorString(e));
+  const Scale sc = s->un.scale();
+  void* u = s->u(s->cur);
+  if (on_device) {
+    if (s->f32)
+      launch_import<float>(data, n, u, n, 0, n, kind, sc, s->p.gamma, s->stream);
+    else
+      launch_import<double>(data, n, u, n, 0, n, kind, sc, s->p.gamma, s->stream);
+    HIP_TRY(hipGetLastError());
+  } else {
+    // host data: chunks of stage_cells cells through the staging region
+    double* st = (double*)(s->ws + s->L.stage);
+    const long long cm = s->L.stage_cells;
+    for (long long c0 = 0; c0 < n; c0 += cm) {
+      const long long m = n - c0 < cm ? n - c0 : cm;
+      HIP_TRY(hipMemcpy2DAsync(st, sizeof(double) * m, data + c0, sizeof(double) * n,
+                               sizeof(double) * m, NV, hipMemcpyHostToDevice, s->stream));
+      if (s->f32)
+        launch_import<float>(st, m, u, n, c0, m, kind, sc, s->p.gamma, s->stream);
+      else
+        launch_import<double>(st, m, u, n, c0, m, kind, sc, s->p.gamma, s->stream);
+      HIP_TRY(hipGetLastError());
     }
-    src = tmp;
   }
-  if (s->f32)
-    launch_import<float>(src, s->u(s->cur), n, kind, s->un.scale(), s->p.gamma, s->stream);
-  else
-    launch_import<double>(src, s->u(s->cur), n, kind, s->un.scale(), s->p.gamma, s->stream);
-  if (s->trc())
-    (void)hipMemsetAsync(s->tr(s->cur), 0, (s->f32 ? 4 : 8) * (size_t)n, s->stream);
+  if (s->trc()) HIP_TRY(hipMemsetAsync(s->tr(s->cur), 0, (s->f32 ? 4 : 8) * (size_t)n, s->stream));
   hipError_t e = hipStreamSynchronize(s->stream);
-  if (tmp) (void)hipFree(tmp);
   if (e != hipSuccess) return fail(ICR_ERR_HIP, "state import failed: %s", hipGetErrorString(e));
   DevClock c;
   int rc = s->read_clock(&c);
@@ -711,24 +745,30 @@ int icr_get_state(icr_solver* s, double* out, int kind, int on_device) {
     return fail(ICR_ERR_ARG, "unknown state kind %d", kind);
   if (!s->have_state) return fail(ICR_ERR_STATE, "no state yet");
   const long long n = s->ncell();
-  const size_t bytes = sizeof(double) * NV * (size_t)n;
-  double* dst = out;
-  double* tmp = nullptr;
-  if (!on_device) {
-    HIP_TRY(hipMalloc(&tmp, bytes));
-    dst = tmp;
+  const Scale sc = s->un.scale();
+  const void* u = s->u(s->cur);
+  if (on_device) {
+    if (s->f32)
+      launch_export<float>(u, n, 0, n, out, n, kind, sc, s->p.gamma, s->stream);
+    else
+      launch_export<double>(u, n, 0, n, out, n, kind, sc, s->p.gamma, s->stream);
+    HIP_TRY(hipGetLastError());
+  } else {
+    double* st = (double*)(s->ws + s->L.stage);
+    const long long cm = s->L.stage_cells;
+    for (long long c0 = 0; c0 < n; c0 += cm) {
+      const long long m = n - c0 < cm ? n - c0 : cm;
+      if (s->f32)
+        launch_export<float>(u, n, c0, m, st, m, kind, sc, s->p.gamma, s->stream);
+      else
+        launch_export<double>(u, n, c0, m, st, m, kind, sc, s->p.gamma, s->stream);
+      HIP_TRY(hipGetLastError());
+      HIP_TRY(hipMemcpy2DAsync(out + c0, sizeof(double) * n, st, sizeof(double) * m,
+                               sizeof(double) * m, NV, hipMemcpyDeviceToHost, s->stream));
+    }
   }
-  if (s->f32)
-    launch_export<float>(s->u(s->cur), dst, n, kind, s->un.scale(), s->p.gamma, s->stream);
-  else
-    launch_export<double>(s->u(s->cur), dst, n, kind, s->un.scale(), s->p.gamma, s->stream);
-  hipError_t e = hipSuccess;
-  if (tmp) e = hipMemcpyAsync(out, tmp, bytes, hipMemcpyDeviceToHost, s->stream);
-  hipError_t e2 = hipStreamSynchronize(s->stream);
-  if (tmp) (void)hipFree(tmp);
-  if (e != hipSuccess || e2 != hipSuccess)
-    return fail(ICR_ERR_HIP, "state export failed: %s",
-                hipGetErrorString(e != hipSuccess ? e : e2));
+  hipError_t e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return fail(ICR_ERR_HIP, "state export failed: %s", hipGetErrorString(e));
   return ICR_OK;
 }
 
@@ -768,6 +808,24 @@ int icr_set_clock_code(icr_solver* s, double t_code, long long step) {
   return set_clock_code(s, t_code, step);
 }
 
+static int step_report(icr_solver* s, icr_step_info* info) {
+  HIP_TRY(hipGetLastError());
+  DevClock c;
+  int rc = s->read_clock(&c);
+  if (rc) return rc;
+  if (info) {
+    info->steps_taken = (int)c.taken;
+    info->status = c.bad == BAD_NONE ? ICR_OK : ICR_ERR_NONPHYSICAL;
+    info->bad_cell = c.bad == BAD_NONE ? -1 : c.bad;
+    info->t = c.t * s->un.t;
+    info->last_dt = c.last_dt * s->un.t;
+    info->residual = c.resid;
+  }
+  if (c.bad != BAD_NONE)
+    return fail(ICR_ERR_NONPHYSICAL, "non-physical cell %d after step %lld", c.bad, c.step);
+  return ICR_OK;
+}
+
 int icr_step(icr_solver* s, int n, double t_end_s, icr_step_info* info) {
   if (!s) return fail(ICR_ERR_ARG, "solver is NULL");
   if (n < 0) return fail(ICR_ERR_ARG, "n_steps must be >= 0");
@@ -794,21 +852,7 @@ int icr_step(icr_solver* s, int n, double t_end_s, icr_step_info* info) {
       s->cur ^= 1;
     }
   }
-  HIP_TRY(hipGetLastError());
-  DevClock c;
-  int rc = s->read_clock(&c);
-  if (rc) return rc;
-  if (info) {
-    info->steps_taken = (int)c.taken;
-    info->status = c.bad == BAD_NONE ? ICR_OK : ICR_ERR_NONPHYSICAL;
-    info->bad_cell = c.bad == BAD_NONE ? -1 : c.bad;
-    info->t = c.t * s->un.t;
-    info->last_dt = c.last_dt * s->un.t;
-    info->residual = c.resid;
-  }
-  if (c.bad != BAD_NONE)
-    return fail(ICR_ERR_NONPHYSICAL, "non-physical cell %d after step %lld", c.bad, c.step);
-  return ICR_OK;
+  return step_report(s, info);
 }
 
 int icr_set_probes(icr_solver* s, int n, int npts, const double* traj, double cadence) {
@@ -886,7 +930,7 @@ int icr_read_probe_log(icr_solver* s, double* out, int cap, int* n_rec) {
 int icr_boundary_at(icr_solver* s, double t_s, double* out) {
   if (!s || !out) return fail(ICR_ERR_ARG, "NULL argument");
   if (!s->have_maps) return fail(ICR_ERR_STATE, "set boundary maps first");
-  double* d = (double*)(s->ws + s->L.bout);
+  double* d = (double*)(s->ws + s->L.stage);
   launch_boundary_at(s->bnd(), t_s / s->un.t, d, s->un.scale(), s->stream);
   HIP_TRY(hipGetLastError());
   const size_t bytes = sizeof(double) * NV * s->g.n_theta * s->g.n_phi;
@@ -900,8 +944,8 @@ int icr_sample_shell(icr_solver* s, double r_m, double* out) {
   if (!s->have_state) return fail(ICR_ERR_STATE, "no state yet");
   if (!(r_m > 0.0)) return fail(ICR_ERR_ARG, "r must be > 0");
   const int nt = s->g.n_theta, np = s->g.n_phi;
-  // the boundary-output buffer holds [8][nt][np] doubles; the shell needs [2][nt][np]
-  double* d = (double*)(s->ws + s->L.bout);
+  // the staging region holds [8][nt][np] doubles; the shell needs [2][nt][np]
+  double* d = (double*)(s->ws + s->L.stage);
   const double* rc = s->m64() + 8LL * s->g.n_r;
   if (s->f32)
     launch_shell<float>(s->u(s->cur), rc, s->g.n_r, nt, np, r_m / s->un.len, s->p.gamma,
@@ -920,24 +964,26 @@ int icr_set_tracer(icr_solver* s, const double* tau, int on_device) {
   if (!s->trc()) return fail(ICR_ERR_STATE, "solver created without the tracer");
   if (!s->have_state) return fail(ICR_ERR_STATE, "set the state first");
   const long long n = s->ncell();
-  double* src = (double*)tau;
-  double* tmp = nullptr;
-  if (!on_device) {
-    HIP_TRY(hipMalloc(&tmp, sizeof(double) * (size_t)n));
-    hipError_t e = hipMemcpyAsync(tmp, tau, sizeof(double) * (size_t)n, hipMemcpyHostToDevice,
-                                  s->stream);
-    if (e != hipSuccess) {
-      (void)hipFree(tmp);
-      return fail(ICR_ERR_HIP, "copy of the tracer failed: %s", hipGetErrorString(e));
+  if (on_device) {
+    if (s->f32)
+      launch_tracer_io<float>(s->u(s->cur), s->tr(s->cur), (double*)tau, 0, n, 1, s->stream);
+    else
+      launch_tracer_io<double>(s->u(s->cur), s->tr(s->cur), (double*)tau, 0, n, 1, s->stream);
+    HIP_TRY(hipGetLastError());
+  } else {
+    double* st = (double*)(s->ws + s->L.stage);
+    const long long cm = s->L.stage_cells;
+    for (long long c0 = 0; c0 < n; c0 += cm) {
+      const long long m = n - c0 < cm ? n - c0 : cm;
+      HIP_TRY(hipMemcpyAsync(st, tau + c0, sizeof(double) * m, hipMemcpyHostToDevice, s->stream));
+      if (s->f32)
+        launch_tracer_io<float>(s->u(s->cur), s->tr(s->cur), st, c0, m, 1, s->stream);
+      else
+        launch_tracer_io<double>(s->u(s->cur), s->tr(s->cur), st, c0, m, 1, s->stream);
+      HIP_TRY(hipGetLastError());
     }
-    src = tmp;
   }
-  if (s->f32)
-    launch_tracer_io<float>(s->u(s->cur), s->tr(s->cur), src, n, 1, s->stream);
-  else
-    launch_tracer_io<double>(s->u(s->cur), s->tr(s->cur), src, n, 1, s->stream);
   hipError_t e = hipStreamSynchronize(s->stream);
-  if (tmp) (void)hipFree(tmp);
   if (e != hipSuccess) return fail(ICR_ERR_HIP, "tracer import failed: %s", hipGetErrorString(e));
   return ICR_OK;
 }
@@ -947,24 +993,27 @@ int icr_get_tracer(icr_solver* s, double* tau, int on_device) {
   if (!s->trc()) return fail(ICR_ERR_STATE, "solver created without the tracer");
   if (!s->have_state) return fail(ICR_ERR_STATE, "no state yet");
   const long long n = s->ncell();
-  double* dst = tau;
-  double* tmp = nullptr;
-  if (!on_device) {
-    HIP_TRY(hipMalloc(&tmp, sizeof(double) * (size_t)n));
-    dst = tmp;
+  if (on_device) {
+    if (s->f32)
+      launch_tracer_io<float>(s->u(s->cur), s->tr(s->cur), tau, 0, n, 0, s->stream);
+    else
+      launch_tracer_io<double>(s->u(s->cur), s->tr(s->cur), tau, 0, n, 0, s->stream);
+    HIP_TRY(hipGetLastError());
+  } else {
+    double* st = (double*)(s->ws + s->L.stage);
+    const long long cm = s->L.stage_cells;
+    for (long long c0 = 0; c0 < n; c0 += cm) {
+      const long long m = n - c0 < cm ? n - c0 : cm;
+      if (s->f32)
+        launch_tracer_io<float>(s->u(s->cur), s->tr(s->cur), st, c0, m, 0, s->stream);
+      else
+        launch_tracer_io<double>(s->u(s->cur), s->tr(s->cur), st, c0, m, 0, s->stream);
+      HIP_TRY(hipGetLastError());
+      HIP_TRY(hipMemcpyAsync(tau + c0, st, sizeof(double) * m, hipMemcpyDeviceToHost, s->stream));
+    }
   }
-  if (s->f32)
-    launch_tracer_io<float>(s->u(s->cur), s->tr(s->cur), dst, n, 0, s->stream);
-  else
-    launch_tracer_io<double>(s->u(s->cur), s->tr(s->cur), dst, n, 0, s->stream);
-  hipError_t e = hipSuccess;
-  if (tmp) e = hipMemcpyAsync(tau, tmp, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost,
-                              s->stream);
-  hipError_t e2 = hipStreamSynchronize(s->stream);
-  if (tmp) (void)hipFree(tmp);
-  if (e != hipSuccess || e2 != hipSuccess)
-    return fail(ICR_ERR_HIP, "tracer export failed: %s",
-                hipGetErrorString(e != hipSuccess ? e : e2));
+  hipError_t e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return fail(ICR_ERR_HIP, "tracer export failed: %s", hipGetErrorString(e));
   return ICR_OK;
 }
 
@@ -972,26 +1021,25 @@ int icr_divv(icr_solver* s, double* out, int on_device) {
   if (!s || !out) return fail(ICR_ERR_ARG, "NULL argument");
   if (!s->have_state || !s->have_maps) return fail(ICR_ERR_STATE, "maps and state first");
   const long long n = s->ncell();
-  double* dst = out;
-  double* tmp = nullptr;
-  if (!on_device) {
-    HIP_TRY(hipMalloc(&tmp, sizeof(double) * (size_t)n));
-    dst = tmp;
-  }
   const double inv_t = 1.0 / s->un.t;
-  if (s->f32)
-    launch_divv<float>(s->stage_args<float>(s->cur, s->cur, s->cur, 0), s->bnd(), inv_t, dst,
-                       s->stream);
-  else
-    launch_divv<double>(s->stage_args<double>(s->cur, s->cur, s->cur, 0), s->bnd(), inv_t, dst,
-                        s->stream);
-  hipError_t e = hipGetLastError();
-  if (tmp && e == hipSuccess)
-    e = hipMemcpyAsync(out, tmp, sizeof(double) * (size_t)n, hipMemcpyDeviceToHost, s->stream);
-  hipError_t e2 = hipStreamSynchronize(s->stream);
-  if (tmp) (void)hipFree(tmp);
-  if (e != hipSuccess || e2 != hipSuccess)
-    return fail(ICR_ERR_HIP, "divergence failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+  // host output: chunks through the staging region
+  const long long cm = on_device ? n : s->L.stage_cells;
+  double* st = (double*)(s->ws + s->L.stage);
+  for (long long c0 = 0; c0 < n; c0 += cm) {
+    const long long m = n - c0 < cm ? n - c0 : cm;
+    double* dst = on_device ? out : st;
+    if (s->f32)
+      launch_divv<float>(s->stage_args<float>(s->cur, s->cur, s->cur, 0), s->bnd(), inv_t, c0, m,
+                         dst, s->stream);
+    else
+      launch_divv<double>(s->stage_args<double>(s->cur, s->cur, s->cur, 0), s->bnd(), inv_t, c0,
+                          m, dst, s->stream);
+    HIP_TRY(hipGetLastError());
+    if (!on_device)
+      HIP_TRY(hipMemcpyAsync(out + c0, st, sizeof(double) * m, hipMemcpyDeviceToHost, s->stream));
+  }
+  hipError_t e = hipStreamSynchronize(s->stream);
+  if (e != hipSuccess) return fail(ICR_ERR_HIP, "divergence failed: %s", hipGetErrorString(e));
   return ICR_OK;
 }
 
@@ -1020,6 +1068,16 @@ int icr_profile_steps(icr_solver* s, int n, double* avg_ms) {
   for (int q = 0; q < 5; ++q) (void)hipEventDestroy(ev[q]);
   for (int k = 0; k < 4; ++k) avg_ms[k] = acc[k] / n;
   return rc;
+}
+
+int icr_fast_math(const double* x, long long n, double* rcp, double* sq, void* stream) {
+  if (n < 0) return fail(ICR_ERR_ARG, "n must be >= 0");
+  if (n > 0 && (!x || !rcp || !sq)) return fail(ICR_ERR_ARG, "NULL argument");
+  if (n == 0) return ICR_OK;
+  launch_fast_math(x, n, rcp, sq, (hipStream_t)stream);
+  HIP_TRY(hipGetLastError());
+  HIP_TRY(hipStreamSynchronize((hipStream_t)stream));
+  return ICR_OK;
 }
 
 int icr_set_launch(icr_solver* s, int variant, int tile_r, int planes, int use_graphs) {

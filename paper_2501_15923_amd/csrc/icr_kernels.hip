@@ -162,6 +162,17 @@ __device__ __forceinline__ void load_prim(const StageArgs<R>& a, int i, int j, i
     const long long g = (long long)k * a.nt + j;
 #pragma unroll
     for (int v = 0; v < NV; ++v) w[v] = a.ghost[v * plane + g];
+    if (a.asymm) {  // transverse parts: minus the mirror cell -1 - i
+      const long long c = ((long long)k * a.nt + j) * a.nr + (-1 - i);
+      R u[NV], wm[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) u[v] = a.uin[v * a.ncell + c];
+      cons2prim<R>(u, wm, a.gm1);
+      w[2] = -wm[2];
+      w[3] = -wm[3];
+      w[6] = -wm[6];
+      w[7] = -wm[7];
+    }
     return;
   }
   if (i >= a.nr) i = a.nr - 1;
@@ -419,57 +430,61 @@ template void launch_init_radial<float>(const BndArgs&, const double*, void*, in
                                         hipStream_t);
 
 // kind 0: primitive SI <-> state; kind 1: conservative code units <-> state.
+// Cells c0 .. c0+m-1 of the state (variable stride ncell); the buffer holds
+// those m cells with variable stride ld (ld = ncell, c0 = 0 for a whole
+// state in place, ld = m for a staging chunk).
 template <typename R>
-__global__ void k_import(const double* __restrict__ in, R* __restrict__ u, long long n, int kind,
-                         Scale sc, double gam) {
+__global__ void k_import(const double* __restrict__ in, long long ld, R* __restrict__ u,
+                         long long ncell, long long c0, long long m, int kind, Scale sc,
+                         double gam) {
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n) return;
+  if (c >= m) return;
   double a[NV], uu[NV];
-  for (int v = 0; v < NV; ++v) a[v] = in[v * n + c];
+  for (int v = 0; v < NV; ++v) a[v] = in[v * ld + c];
   if (kind == 0) {
     for (int v = 0; v < NV; ++v) a[v] /= sc.s[v];
     prim2cons<double>(a, uu, 1.0 / (gam - 1.0));
   } else {
     for (int v = 0; v < NV; ++v) uu[v] = a[v];
   }
-  for (int v = 0; v < NV; ++v) u[v * n + c] = (R)uu[v];
+  for (int v = 0; v < NV; ++v) u[v * ncell + c0 + c] = (R)uu[v];
 }
 
 template <typename R>
-__global__ void k_export(const R* __restrict__ u, double* __restrict__ out, long long n, int kind,
-                         Scale sc, double gam) {
+__global__ void k_export(const R* __restrict__ u, long long ncell, long long c0, long long m,
+                         double* __restrict__ out, long long ld, int kind, Scale sc, double gam) {
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n) return;
+  if (c >= m) return;
   double uu[NV], w[NV];
-  for (int v = 0; v < NV; ++v) uu[v] = (double)u[v * n + c];
+  for (int v = 0; v < NV; ++v) uu[v] = (double)u[v * ncell + c0 + c];
   if (kind == 0) {
     cons2prim<double>(uu, w, gam - 1.0);
-    for (int v = 0; v < NV; ++v) out[v * n + c] = w[v] * sc.s[v];
+    for (int v = 0; v < NV; ++v) out[v * ld + c] = w[v] * sc.s[v];
   } else {
-    for (int v = 0; v < NV; ++v) out[v * n + c] = uu[v];
+    for (int v = 0; v < NV; ++v) out[v * ld + c] = uu[v];
   }
 }
 
 template <typename R>
-void launch_import(const double* in, void* u, long long n, int kind, const Scale& sc, double gam,
-                   hipStream_t s) {
-  hipLaunchKernelGGL(k_import<R>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, in, (R*)u,
-                     n, kind, sc, gam);
+void launch_import(const double* in, long long ld, void* u, long long ncell, long long c0,
+                   long long m, int kind, const Scale& sc, double gam, hipStream_t s) {
+  hipLaunchKernelGGL(k_import<R>, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, in, ld,
+                     (R*)u, ncell, c0, m, kind, sc, gam);
 }
 template <typename R>
-void launch_export(const void* u, double* out, long long n, int kind, const Scale& sc, double gam,
-                   hipStream_t s) {
-  hipLaunchKernelGGL(k_export<R>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                     (const R*)u, out, n, kind, sc, gam);
+void launch_export(const void* u, long long ncell, long long c0, long long m, double* out,
+                   long long ld, int kind, const Scale& sc, double gam, hipStream_t s) {
+  hipLaunchKernelGGL(k_export<R>, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s,
+                     (const R*)u, ncell, c0, m, out, ld, kind, sc, gam);
 }
-template void launch_import<double>(const double*, void*, long long, int, const Scale&, double,
-                                    hipStream_t);
-template void launch_import<float>(const double*, void*, long long, int, const Scale&, double,
-                                   hipStream_t);
-template void launch_export<double>(const void*, double*, long long, int, const Scale&, double,
-                                    hipStream_t);
-template void launch_export<float>(const void*, double*, long long, int, const Scale&, double,
-                                   hipStream_t);
+template void launch_import<double>(const double*, long long, void*, long long, long long,
+                                    long long, int, const Scale&, double, hipStream_t);
+template void launch_import<float>(const double*, long long, void*, long long, long long,
+                                   long long, int, const Scale&, double, hipStream_t);
+template void launch_export<double>(const void*, long long, long long, long long, double*,
+                                    long long, int, const Scale&, double, hipStream_t);
+template void launch_export<float>(const void*, long long, long long, long long, double*,
+                                   long long, int, const Scale&, double, hipStream_t);
 
 // ---------------------------------------------------------------- probes --
 // Primitive rho and v_r on the sphere r (code units) for every (theta, phi)
@@ -585,25 +600,28 @@ void launch_tracer(const TracerArgs<R>& a, int stage, hipStream_t s) {
 template void launch_tracer<double>(const TracerArgs<double>&, int, hipStream_t);
 template void launch_tracer<float>(const TracerArgs<float>&, int, hipStream_t);
 
+// cells c0 .. c0+m-1; tau holds those m cells
 template <typename R>
 __global__ void k_tracer_io(const R* __restrict__ u, R* __restrict__ t, double* __restrict__ tau,
-                            long long n, int to_state) {
+                            long long c0, long long m, int to_state) {
   const long long c = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n) return;
+  if (c >= m) return;
   if (to_state)
-    t[c] = u[c] * (R)tau[c];
+    t[c0 + c] = u[c0 + c] * (R)tau[c];
   else
-    tau[c] = (double)(t[c] / u[c]);
+    tau[c] = (double)(t[c0 + c] / u[c0 + c]);
 }
 
 template <typename R>
-void launch_tracer_io(const void* u, void* t, double* tau, long long n, int to_state,
-                      hipStream_t s) {
-  hipLaunchKernelGGL(k_tracer_io<R>, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s,
-                     (const R*)u, (R*)t, tau, n, to_state);
+void launch_tracer_io(const void* u, void* t, double* tau, long long c0, long long m,
+                      int to_state, hipStream_t s) {
+  hipLaunchKernelGGL(k_tracer_io<R>, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s,
+                     (const R*)u, (R*)t, tau, c0, m, to_state);
 }
-template void launch_tracer_io<double>(const void*, void*, double*, long long, int, hipStream_t);
-template void launch_tracer_io<float>(const void*, void*, double*, long long, int, hipStream_t);
+template void launch_tracer_io<double>(const void*, void*, double*, long long, long long, int,
+                                       hipStream_t);
+template void launch_tracer_io<float>(const void*, void*, double*, long long, long long, int,
+                                      hipStream_t);
 
 // ------------------------------------------------- velocity divergence --
 // Finite-volume divergence of the co-rotating-frame velocity with face
@@ -612,10 +630,11 @@ template void launch_tracer_io<float>(const void*, void*, double*, long long, in
 // v_theta negated beyond the colatitude edges, periodic phi), in 1/s.
 template <typename R>
 __global__ void __launch_bounds__(256) k_divv(StageArgs<R> a, BndArgs b, double inv_time,
-                                              double* out) {
-  const long long c =
+                                              long long c0, long long m, double* out) {
+  const long long q =
       (long long)xcd_tile(blockIdx.x, gridDim.x) * blockDim.x + threadIdx.x;
-  if (c >= a.ncell) return;
+  if (q >= m) return;
+  const long long c = c0 + q;
   const int nr = a.nr, nt = a.nt, np = a.np;
   const int i = (int)(c % nr);
   const long long col = c / nr;
@@ -645,19 +664,19 @@ __global__ void __launch_bounds__(256) k_divv(StageArgs<R> a, BndArgs b, double 
   const R d = (a.m.rp2[i] * vr1 - a.m.rm2[i] * vr0) * a.m.ivr[i] +
               hr * (a.m.sp[j] * vt1 - a.m.sm[j] * vt0) * a.m.ict[j] +
               hr * a.m.phf[j] * (vp1 - vp0);
-  out[c] = (double)d * inv_time;
+  out[q] = (double)d * inv_time;
 }
 
 template <typename R>
-void launch_divv(const StageArgs<R>& a, const BndArgs& b, double inv_time_unit, double* out,
-                 hipStream_t s) {
-  hipLaunchKernelGGL(k_divv<R>, dim3((unsigned)((a.ncell + 255) / 256)), dim3(256), 0, s, a, b,
-                     inv_time_unit, out);
+void launch_divv(const StageArgs<R>& a, const BndArgs& b, double inv_time_unit, long long c0,
+                 long long m, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_divv<R>, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, a, b,
+                     inv_time_unit, c0, m, out);
 }
-template void launch_divv<double>(const StageArgs<double>&, const BndArgs&, double, double*,
-                                  hipStream_t);
-template void launch_divv<float>(const StageArgs<float>&, const BndArgs&, double, double*,
-                                 hipStream_t);
+template void launch_divv<double>(const StageArgs<double>&, const BndArgs&, double, long long,
+                                  long long, double*, hipStream_t);
+template void launch_divv<float>(const StageArgs<float>&, const BndArgs&, double, long long,
+                                 long long, double*, hipStream_t);
 
 template <typename R>
 __global__ void k_probe_sample(ProbeArgs a, const DevClock* __restrict__ ck,
@@ -675,5 +694,23 @@ template void launch_probe_sample<double>(const ProbeArgs&, const DevClock*, con
                                           hipStream_t);
 template void launch_probe_sample<float>(const ProbeArgs&, const DevClock*, const void*, double*,
                                          hipStream_t);
+
+
+// ------------------------------------------------ accuracy diagnostics --
+// The FP64 reciprocal and square root of the face-once stage kernels
+// (rcp_fast, sqrt_fast) on arbitrary inputs.
+__global__ void k_fast_math(const double* __restrict__ x, long long n, double* __restrict__ rcp,
+                            double* __restrict__ sq) {
+  const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  const double v = x[q];
+  rcp[q] = rcp_fast(v);
+  sq[q] = sqrt_fast(v);
+}
+
+void launch_fast_math(const double* x, long long n, double* rcp, double* sq, hipStream_t s) {
+  hipLaunchKernelGGL(k_fast_math, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, x, n, rcp,
+                     sq);
+}
 
 }  // namespace icr

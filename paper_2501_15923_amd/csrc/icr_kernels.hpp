@@ -64,6 +64,9 @@ struct StageArgs {
   R gam, gm1, igm1, omega;
   double cfl;
   int gravity, corot;
+  // 1: v_theta, v_phi, B_theta, B_phi of inner ghost layer g are minus those
+  // of active cell g-1 (the paper's asymm rule); 0: the ghost primitives
+  int asymm;
   // optional (passive tracer on): face mass fluxes of this stage, the lower
   // r / theta / phi face of every cell [3][ncell], the outer r face [np][nt]
   // and the upper theta face of the last row [np][nr]
@@ -330,12 +333,14 @@ void launch_cfl(const StageArgs<R>& a, dim3 grid, dim3 blk, hipStream_t s);
 template <typename R>
 void launch_init_radial(const BndArgs& b, const double* m64, void* u, int nr, double gam,
                         hipStream_t s);
+// cells c0 .. c0+m-1 of a state with ncell cells; the double buffer holds
+// them with variable stride ld
 template <typename R>
-void launch_import(const double* in, void* u, long long n, int kind, const Scale& sc, double gam,
-                   hipStream_t s);
+void launch_import(const double* in, long long ld, void* u, long long ncell, long long c0,
+                   long long m, int kind, const Scale& sc, double gam, hipStream_t s);
 template <typename R>
-void launch_export(const void* u, double* out, long long n, int kind, const Scale& sc, double gam,
-                   hipStream_t s);
+void launch_export(const void* u, long long ncell, long long c0, long long m, double* out,
+                   long long ld, int kind, const Scale& sc, double gam, hipStream_t s);
 template <typename R>
 void launch_probe_sample(const ProbeArgs& a, const DevClock* ck, const void* u, double* out,
                          hipStream_t s);
@@ -344,13 +349,13 @@ void launch_tracer(const TracerArgs<R>& a, int stage, hipStream_t s);
 // tau [np][nt][nr] (host layout, device memory) <-> rho tau, with rho the
 // density of state u
 template <typename R>
-void launch_tracer_io(const void* u, void* t, double* tau, long long n, int to_state,
-                      hipStream_t s);
-// velocity divergence [1/s] of state a.uin; inner ghost from the boundary
-// maps / CMEs at the clock's time
+void launch_tracer_io(const void* u, void* t, double* tau, long long c0, long long m,
+                      int to_state, hipStream_t s);
+// velocity divergence [1/s] of cells c0 .. c0+m-1 of state a.uin into
+// out[0 .. m); inner ghost from the boundary maps / CMEs at the clock's time
 template <typename R>
-void launch_divv(const StageArgs<R>& a, const BndArgs& b, double inv_time_unit, double* out,
-                 hipStream_t s);
+void launch_divv(const StageArgs<R>& a, const BndArgs& b, double inv_time_unit, long long c0,
+                 long long m, double* out, hipStream_t s);
 template <typename R>
 void launch_shell(const void* u, const double* rc, int nr, int nt, int np, double r, double gam,
                   const Scale& sc, double* out, hipStream_t s);
@@ -361,6 +366,8 @@ void launch_stage_lds(const StageArgs<R>& a, int stage, int flux, int lim, int t
 // each side carry the r halo.
 __host__ __device__ constexpr int tile_cells_r(int tile_r) { return tile_r - 4; }
 long long stage_lds_blocks(int nr, int nt, int np, int tile_r, int kplanes);
+// rcp_fast / sqrt_fast of n doubles (accuracy diagnostics)
+void launch_fast_math(const double* x, long long n, double* rcp, double* sq, hipStream_t s);
 template <typename R>
 void launch_finalize(DevClock* ck, const double* part, int nblocks, double cfl, int advance,
                      int log_on, const ProbeArgs& pa, const void* u, double* log,

@@ -84,7 +84,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R>& a, int kplanes, i
   const int i = i0 + ti - 2, j = j0 + tj;  // this lane's cell
   const bool inner = ti >= 2 && ti < TR - 2;
   const bool valid = inner && i < nr && j < nt;
-  const int ic = i < 0 ? 0 : (i < nr ? i : nr - 1), jc = j < nt ? j : nt - 1;
+  // column of the own phi ring: the cell itself, the last cell beyond r_out;
+  // below r_in cell 0, or under the asymm rule the mirror cell -1 - i, whose
+  // transverse primitives the ghost takes negated
+  const int ic = i < 0 ? (a.asymm ? (-1 - i < nr ? -1 - i : nr - 1) : 0)
+                       : (i < nr ? i : nr - 1);
+  const int jc = j < nt ? j : nt - 1;
   const int active = a.clock->active;
   // cell offsets within one variable's array (32-bit: below 2^29 cells)
   const unsigned colbase = (unsigned)(jc * nr + ic);  // + k * nt * nr
@@ -98,8 +103,9 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R>& a, int kplanes, i
   const bool lghost = i < 0;
   const unsigned plane_cells = (unsigned)(nt * nr);
   const long long gplane = (long long)nt * np;
-  // The ring of the first tile's two halo lanes below r_in holds cell 0;
-  // those lanes put the inner ghost into LDS instead (see below).
+  // The ring of the first tile's two halo lanes below r_in holds cell 0 (or
+  // the mirror cell); those lanes put the inner ghost into LDS instead (see
+  // below).
   auto load_own = [&](int k, R (&w)[NV]) {
     load_cons_prim<R, true>(a, (unsigned)wrap_phi(k, np) * plane_cells + lbase, w);
     if (flipj) flip_theta(w);
@@ -176,6 +182,12 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R>& a, int kplanes, i
 #pragma unroll
         for (int v = 0; v < NV; ++v) w[v] = ldg(a.ghost + v * gplane, (unsigned)(k * nt + mj));
         if (flipj) flip_theta(w);
+        if (a.asymm) {  // wb: the mirror cell's primitives (already flipped)
+          w[2] = -wb[2];
+          w[3] = -wb[3];
+          w[6] = -wb[6];
+          w[7] = -wb[7];
+        }
 #pragma unroll
         for (int v = 0; v < NV; ++v) sW[v][tj + 2][ti] = w[v];
       } else {

@@ -27,16 +27,16 @@ def make_grid(grid: Grid, max_maps=16, max_cmes=4, max_probes=8, max_traj_pts=10
 
 def make_phys(gamma=1.5, omega=OMEGA_SUN, cfl=0.4, flux=_abi.FLUX_TVDLF,
               limiter=_abi.LIM_MINMOD, precision=64, gravity=True, corotation=True,
-              tracer=False):
+              tracer=False, bc_transverse=_abi.BCT_MAP):
     return _abi.IcrPhys(gamma, omega, cfl, flux, limiter, precision, int(gravity),
-                        int(corotation), int(tracer))
+                        int(corotation), int(tracer), int(bc_transverse))
 
 
 class Solver:
     def __init__(self, grid: Grid, *, gamma=1.5, omega=OMEGA_SUN, cfl=0.4,
                  flux=_abi.FLUX_TVDLF, limiter=_abi.LIM_MINMOD, precision=64,
-                 gravity=True, corotation=True, tracer=False, max_maps=16, max_cmes=4,
-                 max_probes=8,
+                 gravity=True, corotation=True, tracer=False, bc_transverse=_abi.BCT_MAP,
+                 max_maps=16, max_cmes=4, max_probes=8,
                  max_traj_pts=1024, probe_log_rows=0, device=0, stream=None):
         import torch
         self.torch = torch
@@ -45,7 +45,8 @@ class Solver:
         self.device = torch.device("cuda", device)
         self.g = make_grid(grid, max_maps, max_cmes, max_probes, max_traj_pts, probe_log_rows)
         self.p = make_phys(gamma, omega, cfl, flux, limiter, precision, gravity, corotation,
-                           tracer)
+                           tracer, bc_transverse)
+        self.probe_log_rows = probe_log_rows
         nbytes = ctypes.c_size_t()
         check(lib().icr_workspace_bytes(ctypes.byref(self.g), ctypes.byref(self.p),
                                         ctypes.byref(nbytes)))
@@ -65,14 +66,30 @@ class Solver:
         self.n_probes = 0
 
     @classmethod
-    def wrap(cls, handle, grid: Grid):
+    def wrap(cls, handle, grid: Grid, probe_log_rows=0):
         """A view of a solver owned elsewhere (an ensemble run)."""
         self = cls.__new__(cls)
         self.grid = grid
         self.owned = False
         self.h = handle
         self.n_probes = 0
+        self.probe_log_rows = probe_log_rows
         return self
+
+    def _device_tensor(self, a, shape, what):
+        """Check a torch tensor handed to the library by pointer: float64,
+        contiguous, the expected element count, on a GPU."""
+        import torch
+        if a.dtype != torch.float64:
+            raise TypeError(f"{what} must be float64 (got {a.dtype})")
+        if not a.is_contiguous():
+            raise ValueError(f"{what} must be contiguous")
+        if a.numel() != int(np.prod(shape)):
+            raise ValueError(f"{what} must have {int(np.prod(shape))} elements {shape} "
+                             f"(got {a.numel()})")
+        if a.device.type != "cuda":
+            raise ValueError(f"{what} must be on the GPU (got {a.device})")
+        return _abi.dptr(a.data_ptr())
 
     def close(self):
         if getattr(self, "h", None):
@@ -124,7 +141,8 @@ class Solver:
 
     def set_state(self, a, kind=_abi.STATE_PRIM_SI):
         if hasattr(a, "data_ptr"):
-            check(lib().icr_set_state(self.h, _abi.dptr(a.data_ptr()), kind, 1))
+            check(lib().icr_set_state(self.h, self._device_tensor(a, self.shape, "state"),
+                                      kind, 1))
         else:
             a = np.ascontiguousarray(a, dtype=np.float64)
             check(lib().icr_set_state(self.h, _np_ptr(a), kind, 0))
@@ -173,15 +191,21 @@ class Solver:
         return out
 
     def read_probe_log(self, cap=100000):
+        """(records [n][n_probes][12], number logged).  The device log keeps
+        the first probe_log_rows records; logging more raises instead of
+        returning a silently truncated series."""
         out = np.zeros((cap, self.n_probes, 12))
         n = ctypes.c_int()
         check(lib().icr_read_probe_log(self.h, _np_ptr(out), cap, ctypes.byref(n)))
-        return out[:min(n.value, cap)], n.value
+        if n.value > self.probe_log_rows:
+            raise RuntimeError(f"probe log overflow: {n.value} records logged, the device log "
+                               f"holds {self.probe_log_rows} (raise probe_log_rows)")
+        return out[:min(n.value, cap, self.probe_log_rows)], n.value
 
     def set_tracer(self, tau):
         """CME mass fraction tau [n_phi][n_theta][n_r] (scalar broadcasts)."""
         if hasattr(tau, "data_ptr"):
-            check(lib().icr_set_tracer(self.h, _abi.dptr(tau.data_ptr()), 1))
+            check(lib().icr_set_tracer(self.h, self._device_tensor(tau, self.shape[1:], "tau"), 1))
             return
         tau = np.ascontiguousarray(np.broadcast_to(tau, self.shape[1:]), dtype=np.float64)
         check(lib().icr_set_tracer(self.h, _np_ptr(tau), 0))

@@ -74,7 +74,10 @@ def test_workspace_size_and_validation(lib):
         (_grid(lib, max_maps=0), p), (_grid(lib, max_probes=2, max_traj_pts=1), p),
         (g, _phys(lib, gamma=1.0)), (g, _phys(lib, cfl=0.0)), (g, _phys(lib, cfl=1.5)),
         (g, _phys(lib, flux=7)), (g, _phys(lib, limiter=3)), (g, _phys(lib, limiter=4)), (g, _phys(lib, precision=16)),
-        (g, _phys(lib, tracer=2)),
+        (g, _phys(lib, tracer=2)), (g, _phys(lib, bc_transverse=2)),
+        # asymm mirrors active cells into the ghost layers: n_r >= ghost width
+        (_grid(lib, n_r=1), _phys(lib, bc_transverse=1)),
+        (_grid(lib, n_r=2), _phys(lib, bc_transverse=1, limiter=2)),
     ]
     for gg, pp in bad:
         rc = L.icr_workspace_bytes(ctypes.byref(gg), ctypes.byref(pp), ctypes.byref(n))

@@ -37,14 +37,15 @@ def mods():
 
 
 def pair(mods, grid, times, maps, cmes=None, *, flux=0, limiter=0, gravity=True, corot=True,
-         omega=synth.OMEGA_SUN, gamma=1.5, cfl=0.4, precision=64, **kw):
+         omega=synth.OMEGA_SUN, gamma=1.5, cfl=0.4, precision=64, bc_transverse=0, **kw):
     oracle, solver, _ = mods
     s = solver.Solver(grid, flux=flux, limiter=limiter, gravity=gravity, corotation=corot,
-                      omega=omega, gamma=gamma, cfl=cfl, precision=precision, **kw)
+                      omega=omega, gamma=gamma, cfl=cfl, precision=precision,
+                      bc_transverse=bc_transverse, **kw)
     o = oracle.Oracle(grid.nr, grid.nt, grid.np_, flux=flux, limiter=limiter, gravity=gravity,
                       corot=corot, omega=omega, gamma=gamma, cfl=cfl,
                       r_in=grid.r_in, r_out=grid.r_out, th_min=grid.th_min,
-                      th_max=grid.th_max)
+                      th_max=grid.th_max, bc_transverse=bc_transverse)
     s.set_maps(times, maps)
     o.set_maps(times, maps)
     if cmes is not None:
@@ -279,18 +280,44 @@ def test_probe_log_cadence_parity(mods):
             assert np.max(np.abs(a[:, v] - b[:, v])) / scale < 1e-9
 
 
+@pytest.mark.timeout(600)
 @pytest.mark.parametrize("what", ["dynamic", "cme"])
 def test_production_grid_parity(mods, what):
-    """600 x 60 x 120 in the bench's launch configuration, a few steps."""
+    """600 x 60 x 120 (10 maps 6 h apart, 4 probes logged), 100 steps in the
+    bench's launch configuration; the CME case starts inside the insertion
+    window, mid-way between two maps, so the cone is written at every
+    stage of the 100 steps."""
     w = configs.prod_dynamic() if what == "dynamic" else configs.prod_cme()
-    s, o = pair(mods, w.grid, w.times, w.maps, w.cmes if len(w.cmes) else None)
+    s, o = pair(mods, w.grid, w.times, w.maps, w.cmes if len(w.cmes) else None,
+                probe_log_rows=256)
     if what == "cme":
-        # start inside the CME insertion window and mid-way between maps
         t0 = w.cmes[0][0] + 600.0
         s.set_clock(t0)
         o.set_clock(t0)
-    say(f"production grid {what}: 3 steps")
-    s.step(3)
-    o.step(3)
+    s.set_probes(w.probes, cadence=w.probe_cadence)
+    say(f"production grid {what}: 100 steps")
+    info = s.step(100)
+    assert info["steps"] == 100 and info["status"] == 0
+    o.step(100)
     e = parity.assert_parity(*cons(mods, s, o), what=f"production {what}")
+    assert abs(s.clock()["t"] / o.clock()["t"] - 1) < 1e-11
+    # the probes at the final time, per group normalised like the state
+    # metric: the probes sit on the equator, next to the current sheet of the
+    # first maps, where the interpolated field nearly cancels, so the field
+    # and velocity errors are taken relative to their largest magnitude on
+    # the grid
+    a, b = s.sample_probes(), o.sample(w.probes)
+    W = o.get_state()
+    for cols, scale in (((4,), None), ((5, 6, 7), np.max(np.abs(W[1:4]))), ((8,), None),
+                        ((9, 10, 11), np.max(np.abs(W[5:8])))):
+        cols = list(cols)
+        if scale is None:
+            scale = np.max(np.abs(b[:, cols]))
+        assert np.max(np.abs(a[:, cols] - b[:, cols])) / scale < 1e-9, cols
+    log, n = s.read_probe_log()
+    if w.probe_cadence == 0.0:
+        assert n == 100
+        assert np.allclose(log[-1][:, 4:], a[:, 4:], rtol=1e-14, atol=0)
+    if what == "cme":  # still inside the insertion window
+        assert s.clock()["t"] < w.cmes[0][0] + w.cmes[0][1]
     say("errors", e)

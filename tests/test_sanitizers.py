@@ -1,0 +1,154 @@
+"""AddressSanitizer runs on the CPU: the oracle (with UndefinedBehavior-
+Sanitizer as well) over a set of small workloads that touch every code
+path, and the host side of the HIP library (argument validation, error
+returns, unit conversion, workspace layout) through the C-ABI without a
+GPU.  Each run is a child Python process with the sanitizer runtime
+preloaded; any report aborts it."""
+import glob
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+PKG = os.path.join(ROOT, "paper_2501_15923_amd")
+
+ORACLE_SCRIPT = r"""
+import sys
+import numpy as np
+sys.path.insert(0, sys.argv[2])
+import oracle
+oracle.LIB_PATH = sys.argv[1]
+oracle._lib = None
+from paper_2501_15923_amd import configs, synth
+w = configs.tiny_static()
+g = synth.Grid(12, 6, 8)
+times, maps = synth.dynamic_maps(g, 3, cadence=600.0)
+cme = np.array([[0.0, 3600.0, 0.1, 1.0, 0.5, 1.0e6, 1e-18, 0.8e6]])
+for flux, lim, bct, trc in ((0, 0, 0, True), (1, 1, 1, False), (2, 2, 0, False), (2, 1, 1, True)):
+    o = oracle.Oracle(g.nr, g.nt, g.np_, flux=flux, limiter=lim, bc_transverse=bct, tracer=trc)
+    o.set_maps(times, maps)
+    o.set_cmes(cme)
+    o.init_radial()
+    info = o.step(5)
+    assert info["status"] == 0, info
+    o.divb(); o.divv(); o.fill_ghosts(100.0); o.inner_boundary(50.0); o.volumes()
+    o.sample(synth.probe_tables(3600.0, 1)[:, :5])
+    if trc:
+        o.set_tracer(0.5); o.get_tracer(); o.tracer_flux()
+    o.get_state(kind=2); o.get_state(kind=0); o.last_boundary_flux(); o.dt()
+s = oracle.Oracle(16, 1, 1, geom=oracle.GEOM_SLAB, gravity=False, corot=False, box=(0, 1, 0, 1, 0, 1))
+W = np.zeros(s.shape); W[0] = 1.0; W[4] = 1.0; W[5] = 0.3
+s.set_state(W, kind=3); s.step(10)
+print("oracle ok")
+"""
+
+HOST_SCRIPT = r"""
+import ctypes, sys
+sys.path.insert(0, sys.argv[2])
+from paper_2501_15923_amd import _abi
+_abi.LIB_PATH = sys.argv[1]
+L = _abi.lib()
+AU = 1.495978707e11
+def grid(**kw):
+    d = dict(n_r=600, n_theta=60, n_phi=120, r_in=0.1 * AU, r_out=2 * AU, th_min=0.5,
+             th_max=2.6, max_maps=10, max_cmes=1, max_probes=4, max_traj_pts=500,
+             probe_log_rows=100)
+    d.update(kw)
+    return _abi.IcrGrid(**d)
+def phys(**kw):
+    d = dict(gamma=1.5, omega=2.87e-6, cfl=0.4, flux=0, limiter=0, precision=64, gravity=1,
+             corotation=1, tracer=0, bc_transverse=0)
+    d.update(kw)
+    return _abi.IcrPhys(**d)
+n = ctypes.c_size_t()
+B = ctypes.byref
+for g, p, want in [(grid(), phys(), 0), (grid(), phys(tracer=1, precision=32), 0),
+                   (grid(n_r=0), phys(), -1), (grid(), phys(cfl=2.0), -1),
+                   (grid(n_r=1), phys(bc_transverse=1), -1), (grid(max_probes=65), phys(), -1),
+                   (grid(n_r=1024, n_theta=1024, n_phi=512), phys(), -1)]:
+    assert L.icr_workspace_bytes(B(g), B(p), B(n)) == want
+    L.icr_last_error()
+gs = (_abi.IcrGrid * 3)(grid(), grid(n_r=150), grid(n_r=0))
+assert L.icr_ens_workspace_bytes(2, gs, B(phys()), B(n)) == 0
+assert L.icr_ens_workspace_bytes(3, gs, B(phys()), B(n)) == -1
+assert L.icr_ens_workspace_bytes(2, gs, B(phys(tracer=1)), B(n)) == -5
+h = ctypes.c_void_p()
+assert L.icr_create(B(grid()), B(phys()), None, 0, None, B(h)) == -1
+assert L.icr_create(B(grid()), B(phys()), ctypes.c_void_p(256), 10, None, B(h)) == -1
+D = ctypes.POINTER(ctypes.c_double)
+for name, args in [("icr_grid_edges", (None, None, None)), ("icr_init_radial", ()),
+                   ("icr_set_boundary_maps", (1, None, None, 0)), ("icr_set_cmes", (0, None)),
+                   ("icr_set_state", (None, 0, 0)), ("icr_get_state", (None, 0, 0)),
+                   ("icr_step", (1, -1.0, None)),
+                   ("icr_set_probes", (0, 0, None, -1.0)), ("icr_sample_probes", (None,)),
+                   ("icr_boundary_at", (0.0, None)), ("icr_sample_shell", (1.0, None)),
+                   ("icr_set_tracer", (None, 0)), ("icr_get_tracer", (None, 0)),
+                   ("icr_divv", (None, 0)), ("icr_set_launch", (0, 0, 0, 1)),
+                   ("icr_profile_steps", (1, None)), ("icr_set_clock", (0.0, 0))]:
+    assert getattr(L, name)(None, *args) == -1, name
+assert L.icr_fast_math(None, 0, None, None, None) == 0
+assert L.icr_fast_math(None, -1, None, None, None) == -1
+out = (ctypes.c_double * 6)()
+assert L.icr_units(out) == 0 and out[1] == AU
+shape = _abi.NnShape(60, 120, 600, 64, 128, 384, 8, -2, 46)
+cnt = ctypes.c_longlong()
+assert L.icr_nn_param_count(B(shape), B(cnt)) == 0 and cnt.value > 2_000_000
+assert L.icr_nn_workspace_bytes(B(shape), B(n)) == 0
+bad = _abi.NnShape(60, 120, 600, 64, 128, 384, 8, 5, 46)
+assert L.icr_nn_param_count(B(bad), B(cnt)) == -1
+L.icr_nn_last_error()
+print("host ok")
+"""
+
+
+def _run(script, lib, preload):
+    env = dict(os.environ, LD_PRELOAD=preload,
+               ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
+               UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1",
+               OMP_NUM_THREADS="2")
+    res = subprocess.run([sys.executable, "-c", script, lib, ROOT], env=env,
+                         capture_output=True, text=True, timeout=600)
+    assert res.returncode == 0, res.stdout[-3000:] + res.stderr[-6000:]
+    assert "AddressSanitizer" not in res.stderr and "runtime error" not in res.stderr, \
+        res.stderr[-6000:]
+    return res.stdout
+
+
+def test_oracle_under_address_and_ub_sanitizers(tmp_path):
+    libasan = subprocess.run(["gcc", "-print-file-name=libasan.so"], capture_output=True,
+                             text=True).stdout.strip()
+    if not os.path.isabs(libasan):
+        pytest.skip("gcc has no libasan")
+    lib = str(tmp_path / "liborc_asan.so")
+    subprocess.check_call(["gcc", "-O1", "-g", "-std=c11", "-fopenmp", "-ffp-contract=off",
+                           "-fPIC", "-shared", "-fsanitize=address,undefined",
+                           "-fno-sanitize-recover=all", "-fno-omit-frame-pointer",
+                           "-o", lib, os.path.join(ROOT, "oracle", "orc_mhd.c"), "-lm"])
+    assert "oracle ok" in _run(ORACLE_SCRIPT, lib, libasan)
+
+
+def test_host_library_under_address_sanitizer(tmp_path):
+    objs = [os.path.join(PKG, "_build", f + ".o")
+            for f in ("icr_kernels", "icr_stage_lds", "icr_ensemble", "icr_nn")]
+    if not all(os.path.exists(o) for o in objs):
+        pytest.skip("build the library first (its object files are linked here)")
+    rt = sorted(glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+    if not rt:
+        pytest.skip("no clang ASan runtime")
+    hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    api_o = str(tmp_path / "icr_api_asan.o")
+    lib = str(tmp_path / "libicarus_asan.so")
+    # host code instrumented, device code as in the product build
+    subprocess.check_call([hipcc, "--offload-arch=gfx950", "-O1", "-g", "-std=c++17", "-fPIC",
+                           "-ffp-contract=on", "-Xclang", "-target-feature", "-Xclang",
+                           "-packed-fp32-ops", "-Xarch_host", "-fsanitize=address",
+                           "-Xarch_host", "-fno-omit-frame-pointer",
+                           "-I" + os.path.join(ROOT, "include"), "-c", "-o", api_o,
+                           os.path.join(PKG, "csrc", "icr_api.hip")],
+                          stderr=subprocess.DEVNULL)
+    subprocess.check_call([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-Xarch_host",
+                           "-fsanitize=address", "-Xarch_host", "-shared-libasan", "-o", lib,
+                           api_o, *objs])
+    assert "host ok" in _run(HOST_SCRIPT, lib, rt[-1])
