@@ -236,6 +236,22 @@ int icr_set_clock_code(icr_solver *s, double t_code, long long step);
  * invalid cell; info may be NULL. */
 int icr_step(icr_solver *s, int n_steps, double t_end_s, icr_step_info *info);
 
+/* For callers that cannot allocate device memory or instantiate graphs
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation): icr_step with direct kernel launches instead of graph
+ * replays, and the stage-2 kernel's per-block CFL / residual / validity
+ * partials in a fixed device array of the library instead of the
+ * workspace.  Same arguments, results and errors as icr_step (bit-identical
+ * states).  The array holds 32768 blocks (1 MiB, one copy per device, kept
+ * until the process ends): a solver whose stage launch has more blocks
+ * gets ICR_ERR_ARG (choose more phi planes per block with icr_set_launch).
+ * Call it with the solver's device current (ICR_ERR_ARG otherwise).  Every
+ * call on one device shares that device's array: calls for different
+ * solvers that overlap in time on one device (other host threads, other
+ * streams) race and must be serialised by the caller.  Nothing in the
+ * array needs to start at zero: each step writes every slot it reads. */
+int icr_step_noalloc(icr_solver *s, int n_steps, double t_end_s, icr_step_info *info);
+
 /* Probes (Sect. 2 particle sampling): n <= max_probes trajectory tables
  * traj [n][n_pts][4] of rows (t [s], r [m], theta, phi_inertial [rad]),
  * ascending t, unwrapped phi, 2 <= n_pts <= max_traj_pts.  Positions are

@@ -80,6 +80,7 @@ SIGNATURES = {
     "icr_set_clock": (I, [P, ctypes.c_double, ctypes.c_longlong]),
     "icr_set_clock_code": (I, [P, ctypes.c_double, ctypes.c_longlong]),
     "icr_step": (I, [P, I, ctypes.c_double, ctypes.POINTER(IcrStepInfo)]),
+    "icr_step_noalloc": (I, [P, I, ctypes.c_double, ctypes.POINTER(IcrStepInfo)]),
     "icr_set_probes": (I, [P, I, I, D, ctypes.c_double]),
     "icr_sample_probes": (I, [P, D]),
     "icr_read_probe_log": (I, [P, D, I, ctypes.POINTER(ctypes.c_int)]),

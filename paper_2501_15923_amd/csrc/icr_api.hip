@@ -9,6 +9,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -173,6 +174,35 @@ int validate(const icr_grid* g, const icr_phys* p) {
   return ICR_OK;
 }
 
+// ---- fixed device array of icr_step_noalloc --------------------------------
+// The per-block CFL / residual / validity partials of the stage-2 kernel (4
+// doubles per block) for callers that cannot allocate.  Each device holds
+// its own copy from module load until the process ends; host code uses the
+// address hipGetSymbolAddress returns for the current device, never the
+// array's name.
+constexpr int NOALLOC_MAX_BLOCKS = 32768;  // 1 MiB
+static __device__ __align__(256) double scratch[4 * NOALLOC_MAX_BLOCKS];
+
+constexpr int MAX_DEVICES = 64;
+std::mutex g_scratch_mu;
+double* g_scratch_ptr[MAX_DEVICES] = {};
+
+// Address of this device's scratch array (looked up once per device, with
+// that device current).
+int scratch_for_device(int dev, double** out) {
+  if (dev < 0 || dev >= MAX_DEVICES) return fail(ICR_ERR_HIP, "device id %d out of range", dev);
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_ptr[dev]) {
+    void* p = nullptr;
+    hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p)
+      return fail(ICR_ERR_HIP, "hipGetSymbolAddress(scratch) failed: %s", hipGetErrorString(e));
+    g_scratch_ptr[dev] = (double*)p;
+  }
+  *out = g_scratch_ptr[dev];
+  return ICR_OK;
+}
+
 }  // namespace
 
 struct icr_solver {
@@ -194,7 +224,7 @@ struct icr_solver {
   hipGraphExec_t g_chunk[2], g_one[2];
   bool graphs_ok;
   int dev;                  // HIP device the solver was created on
-  double* part_override;    // non-null: stage-2 partials go here instead
+  double* part_override;    // non-null: stage-2 partials go here (icr_step_noalloc)
 
   double* partials() { return part_override ? part_override : (double*)(ws + L.partials); }
 
@@ -470,6 +500,14 @@ int icr_create(const icr_grid* g, const icr_phys* p, void* ws, size_t ws_bytes, 
   if (e != hipSuccess) {
     delete s;
     return fail(ICR_ERR_HIP, "hipGetDevice failed: %s", hipGetErrorString(e));
+  }
+  {  // the fixed partials array of icr_step_noalloc on this device
+    double* sp = nullptr;
+    rc = scratch_for_device(s->dev, &sp);
+    if (rc) {
+      delete s;
+      return rc;
+    }
   }
   e = hipStreamCreateWithFlags(&s->cap_stream, hipStreamNonBlocking);
   if (e != hipSuccess) {
@@ -824,6 +862,39 @@ static int step_report(icr_solver* s, icr_step_info* info) {
   if (c.bad != BAD_NONE)
     return fail(ICR_ERR_NONPHYSICAL, "non-physical cell %d after step %lld", c.bad, c.step);
   return ICR_OK;
+}
+
+int icr_step_noalloc(icr_solver* s, int n, double t_end_s, icr_step_info* info) {
+  if (!s) return fail(ICR_ERR_ARG, "solver is NULL");
+  if (n < 0) return fail(ICR_ERR_ARG, "n_steps must be >= 0");
+  if (!s->have_maps) return fail(ICR_ERR_STATE, "set boundary maps first");
+  if (!s->have_state) return fail(ICR_ERR_STATE, "initialise the state first");
+  const int nb = s->stage_blocks();
+  if (nb > NOALLOC_MAX_BLOCKS)
+    return fail(ICR_ERR_ARG,
+                "icr_step_noalloc: the stage launch has %d blocks, the fixed partials array "
+                "holds %d (use more phi planes per block or icr_step)",
+                nb, NOALLOC_MAX_BLOCKS);
+  int dev = -1;
+  HIP_TRY(hipGetDevice(&dev));
+  if (dev != s->dev)
+    return fail(ICR_ERR_ARG, "icr_step_noalloc: solver of device %d called with device %d "
+                "current", s->dev, dev);
+  double* sp = nullptr;
+  int rc = scratch_for_device(s->dev, &sp);  // looked up at creation: no lookup here
+  if (rc) return rc;
+  const double tend = t_end_s > 0.0 ? t_end_s / s->un.t : -1.0;
+  launch_clock_begin(s->clock(), tend, s->stream);
+  // direct launches (no graph instantiation), partials in the fixed array;
+  // every stage-2 block writes its slot before the finalize kernel reads it,
+  // so nothing needs clearing between calls
+  s->part_override = sp;
+  for (int q = 0; q < n; ++q) {
+    s->enqueue_step(s->cur, s->stream);
+    s->cur ^= 1;
+  }
+  s->part_override = nullptr;
+  return step_report(s, info);
 }
 
 int icr_step(icr_solver* s, int n, double t_end_s, icr_step_info* info) {

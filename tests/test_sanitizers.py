@@ -81,7 +81,7 @@ D = ctypes.POINTER(ctypes.c_double)
 for name, args in [("icr_grid_edges", (None, None, None)), ("icr_init_radial", ()),
                    ("icr_set_boundary_maps", (1, None, None, 0)), ("icr_set_cmes", (0, None)),
                    ("icr_set_state", (None, 0, 0)), ("icr_get_state", (None, 0, 0)),
-                   ("icr_step", (1, -1.0, None)),
+                   ("icr_step", (1, -1.0, None)), ("icr_step_noalloc", (1, -1.0, None)),
                    ("icr_set_probes", (0, 0, None, -1.0)), ("icr_sample_probes", (None,)),
                    ("icr_boundary_at", (0.0, None)), ("icr_sample_shell", (1.0, None)),
                    ("icr_set_tracer", (None, 0)), ("icr_get_tracer", (None, 0)),
