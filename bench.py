@@ -55,7 +55,7 @@ def parse():
                          "FETCH_SIZE and WRITE_SIZE of this bench, of --copy-calibration, "
                          "then optionally one with SQ_INSTS_VALU of this bench")
     ap.add_argument("--workload", default="prod",
-                    choices=("prod", "ensemble", "relax", "jupiter"),
+                    choices=("prod", "ensemble", "relax", "jupiter", "fullrun"),
                     help="prod: 600x60x120 dynamic run (the headline line); ensemble: 64 "
                          "runs batched vs the same runs one after the other; relax: warm vs "
                          "plain relaxation on held-out maps; jupiter: 5.5 AU domain with "
@@ -217,6 +217,82 @@ def relax_bench(args):
     print(json.dumps(out), flush=True)
 
 
+def fullrun_bench(args):
+    """The production runs to their end: prod_dynamic (10 maps, 3 simulated
+    days, 4 probes logged every 10 minutes) and prod_cme (plus a cone CME),
+    each in FP64 and FP32, with the default map variant and the configured
+    thinner / stronger-field one.  Reports steps, wall time, whether every
+    step stayed physical (else the step and cell of the first failure), the
+    FP32 error against FP64 (per conserved group, max over the grid / max of
+    the FP64 state) and the relative L2 of the FP32 probe series against the
+    FP64 one."""
+    import numpy as np
+    import torch
+
+    from paper_2501_15923_amd import configs
+    from paper_2501_15923_amd.solver import Solver
+
+    def run(w, prec):
+        g = w.grid
+        s = Solver(g, precision=prec, probe_log_rows=600, max_traj_pts=w.probes.shape[1])
+        s.set_maps(w.times, w.maps)
+        if len(w.cmes):
+            s.set_cmes(w.cmes)
+        s.set_probes(w.probes, cadence=600.0)
+        s.init_radial()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        steps, fail = 0, None
+        while True:
+            info = s.step(2000, t_end=w.t_end, raise_on_error=False)
+            steps += info["steps"]
+            if info["status"] != 0:
+                fail = {"step": s.clock()["step"], "t_h": info["t"] / 3600,
+                        "bad_cell": info["bad_cell"]}
+                break
+            if info["steps"] < 2000:
+                break
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        t = s.clock()["t"]
+        U = s.get_state(kind=1)
+        log_, n = s.read_probe_log()
+        s.close()
+        return dict(steps=steps, wall_s=wall, t_days=t / 86400, fail=fail,
+                    cells_per_s=g.cells * steps / wall), U, log_
+
+    results = []
+    for configured in (False, True):
+        for name in ("prod_dynamic", "prod_cme"):
+            w = getattr(configs, name)(configured_maps=configured)
+            rec = {"workload": w.name,
+                   "maps": configs.CONFIGURED_MAPS_NAME if configured else configs.DEFAULT_MAPS}
+            r64, U64, L64 = run(w, 64)
+            log(f"bench: {w.name} ({rec['maps']}) fp64: {r64}")
+            rec["fp64"] = r64
+            if r64["fail"] is None:
+                r32, U32, L32 = run(w, 32)
+                log(f"bench: {w.name} fp32: {r32}")
+                rec["fp32"] = r32
+                if r32["fail"] is None:
+                    err = {}
+                    for gname, sl in (("rho", slice(0, 1)), ("m", slice(1, 4)),
+                                      ("e", slice(4, 5)), ("B", slice(5, 8))):
+                        err[gname] = float(np.max(np.abs(U32[sl] - U64[sl])) /
+                                           np.max(np.abs(U64[sl])))
+                    rec["fp32_vs_fp64_state"] = err
+                    n = min(len(L32), len(L64))
+                    pe = {}
+                    for vname, c in (("rho", 4), ("v_r", 5), ("p", 8), ("B_r", 9), ("B_phi", 11)):
+                        a, b = L32[:n, :, c], L64[:n, :, c]
+                        ok = np.isfinite(b)
+                        pe[vname] = float(np.linalg.norm((a - b)[ok]) / np.linalg.norm(b[ok]))
+                    rec["fp32_vs_fp64_probe_series_relL2"] = pe
+                    rec["probe_records"] = int(n)
+            results.append(rec)
+    print(json.dumps({"fullrun": results}), flush=True)
+
+
 def jupiter_bench(args):
     """Extended domain to 5.5 AU (803 x 60 x 120 cells), hourly maps streamed
     into a 4-map buffer while the run advances (appends inside the timed
@@ -341,24 +417,53 @@ def ingest_counters(dirs, precision, out_path):
     print(json.dumps(rec), flush=True)
 
 
-def cpu_baseline(w, steps):
-    """The oracle as it stands on the host cores, production grid, `steps`
-    RK2 steps from the radial-expansion state."""
-    import oracle
-    oracle.build()
+def _cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def _oracle_rate(oracle, w, steps):
     g = w.grid
     o = oracle.Oracle(g.nr, g.nt, g.np_)
     o.set_maps(w.times, w.maps)
     o.init_radial()
-    o.step(1)  # first-touch of the work arrays outside the timing
+    o.step(1)  # first touch of the work arrays outside the timing
     t0 = time.perf_counter()
-    o.step(steps)
+    info = o.step(steps)
     dt = time.perf_counter() - t0
-    cores = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return {"value": g.cells * steps / dt, "unit": "cell-updates/s", "cores": cores,
-            "kind": "oracle",
+    assert info["status"] == 0 and info["steps"] == steps
+    return g.cells * steps / dt, dt
+
+
+def cpu_baseline(w, steps):
+    """The oracle as it stands on the host cores: `steps` RK2 steps of the
+    production grid from the radial-expansion state with every OpenMP
+    thread (the reported value), one step single-threaded, and the 64 x 16 x
+    32 correctness workload for its 200 steps."""
+    import oracle
+
+    from paper_2501_15923_amd import configs
+    oracle.build()
+    threads = oracle.threads()
+    rate, dt = _oracle_rate(oracle, w, steps)
+    oracle.set_threads(1)
+    rate1, dt1 = _oracle_rate(oracle, w, 1)
+    oracle.set_threads(threads)
+    tiny = configs.tiny_static()
+    rate_tiny, dt_tiny = _oracle_rate(oracle, tiny, tiny.steps)
+    g = w.grid
+    return {"value": rate, "unit": "cell-updates/s", "cores": threads, "kind": "oracle",
             "sample": f"{steps} RK2 steps of the {g.nr}x{g.nt}x{g.np_} production grid "
-                      f"({dt:.1f} s wall, OpenMP over phi)"}
+                      f"({dt:.1f} s wall, {threads} OpenMP threads over phi)",
+            "cpu_model": _cpu_model(),
+            "single_thread": {"value": rate1, "sample": f"1 step, {dt1:.1f} s"},
+            "tiny_64x16x32_200_steps": {"value": rate_tiny, "wall_s": round(dt_tiny, 2),
+                                        "threads": threads}}
 
 
 def main():
@@ -383,6 +488,9 @@ def main():
     if args.workload == "jupiter":
         jupiter_bench(args)
         return
+    if args.workload == "fullrun":
+        fullrun_bench(args)
+        return
     import numpy as np
     import torch
 
@@ -397,7 +505,15 @@ def main():
     lim = {"minmod": 0, "mc": 1, "weno5": 2}[args.limiter]
     s = Solver(g, precision=args.precision, probe_log_rows=args.steps + args.warmup + 16,
                max_traj_pts=w.probes.shape[1], tracer=args.tracer, flux=flux, limiter=lim)
-    s.set_launch(args.variant, 0, 0, 1)
+    tile_r, planes = 0, 0
+    if args.variant in (0, 2) and not args.tracer and lim != 2:
+        # the launch tuner's choice for this grid (untimed; timed on a
+        # throwaway solver of the same shape)
+        from paper_2501_15923_amd import autotune
+        tile_r, planes = autotune.tune_solver(g, precision=args.precision, flux=flux,
+                                              limiter=lim)
+        log(f"bench: launch tuner chose tile_r {tile_r}, {planes} phi planes per block")
+    s.set_launch(args.variant, tile_r, planes, 1)
     s.set_maps(w.times, w.maps)
     if len(w.cmes):
         s.set_cmes(w.cmes)
@@ -454,8 +570,10 @@ def main():
         "scaling": "weak", "vs_baseline": None, "dtype": f"f{args.precision}",
         "data": "synthetic",
         "config": {"workload": w.name, "cells": g.cells, "maps": len(w.times),
+                   "map_variant": configs.DEFAULT_MAPS,
                    "probes": int(w.probes.shape[0]), "flux": args.flux.upper(), "limiter": args.limiter,
-                   "rk": "SSP-RK2", "cfl": w.cfl, "parallelism": "single GPU"},
+                   "rk": "SSP-RK2", "cfl": w.cfl, "parallelism": "single GPU",
+                   "launch": {"tile_r": tile_r or 64, "phi_planes": planes or 8}},
         "roofline": roof,
     }
     if args.flux != "tvdlf" or args.limiter != "minmod":

@@ -80,12 +80,24 @@ def lib():
         L.orc_divv.argtypes = [P, D]
         L.orc_face_flux.argtypes = [P, D, D, ctypes.c_int, D]
         L.orc_ghosts.argtypes = [P]
+        L.orc_threads.restype = ctypes.c_int
+        L.orc_threads.argtypes = []
+        L.orc_set_threads.argtypes = [ctypes.c_int]
         _lib = L
     return _lib
 
 
 def _d(a: np.ndarray):
     return a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+
+
+def threads() -> int:
+    """OpenMP threads the oracle's loops use."""
+    return lib().orc_threads()
+
+
+def set_threads(n: int) -> None:
+    lib().orc_set_threads(int(n))
 
 
 def units() -> dict:

@@ -30,6 +30,7 @@
  * and stored, and nothing is fused.  Build with -O2 -ffp-contract=off.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -1472,4 +1473,11 @@ void orc_divb(void *h, double *out) {
         double bn = sqrt(b[0] * b[0] + b[1] * b[1] + b[2] * b[2]);
         out[q] = bn > 0.0 ? fabs(div) * hmin / bn : 0.0;
       }
+}
+
+/* OpenMP threads the oracle's parallel loops use, and setting them (the
+ * CPU-baseline timing reports the count actually used). */
+int orc_threads(void) { return omp_get_max_threads(); }
+void orc_set_threads(int n) {
+  if (n > 0) omp_set_num_threads(n);
 }

@@ -41,16 +41,28 @@ def tiny_static(seed: int = 0) -> Workload:
                     np.zeros((0, 8)), None, 200, -1.0)
 
 
-def prod_dynamic(seed: int = 1, nr: int = 600, nt: int = 60, nph: int = 120) -> Workload:
+# The map variant the workloads use by default: rho v_r^2 constant with
+# 300 cm^-3 in the 700 km/s fast wind (1200 cm^-3 at 350 km/s) and
+# B_r = +-150 nT, plasma beta >= 0.36 at 0.1 AU.  CONFIGURED_MAPS is the
+# thinner, stronger-field variant (300 cm^-3 at 350 km/s, 75 cm^-3 in the
+# fast wind, +-250 nT, beta 0.085 in the fast wind).
+DEFAULT_MAPS = "150 nT, 300 cm^-3 fast / 1200 cm^-3 slow wind, 1 MK"
+CONFIGURED_MAPS = dict(b_r=250e-9, n_fast=75e6)
+CONFIGURED_MAPS_NAME = "250 nT, 75 cm^-3 fast / 300 cm^-3 slow wind, 1 MK"
+
+
+def prod_dynamic(seed: int = 1, nr: int = 600, nt: int = 60, nph: int = 120,
+                 configured_maps: bool = False) -> Workload:
     g = Grid(nr, nt, nph)
-    times, maps = synth.dynamic_maps(g, seed)
+    times, maps = synth.dynamic_maps(g, seed, **(CONFIGURED_MAPS if configured_maps else {}))
     probes = synth.probe_tables(3 * DAY, seed)
     return Workload(f"prod_dynamic_{nr}x{nt}x{nph}", g, times, maps,
                     np.zeros((0, 8)), probes, 0, 3 * DAY)
 
 
-def prod_cme(seed: int = 2, nr: int = 600, nt: int = 60, nph: int = 120) -> Workload:
-    w = prod_dynamic(1, nr, nt, nph)
+def prod_cme(seed: int = 2, nr: int = 600, nt: int = 60, nph: int = 120,
+             configured_maps: bool = False) -> Workload:
+    w = prod_dynamic(1, nr, nt, nph, configured_maps)
     cme = synth.cone_cme(seed, w.probes[1])
     w.name = f"prod_cme_{nr}x{nt}x{nph}"
     w.cmes = cme[None]

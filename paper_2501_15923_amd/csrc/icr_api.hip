@@ -70,7 +70,10 @@ struct Units {
   }
 };
 
-constexpr int CHUNK = 16;  // steps per captured graph (even: parity kept)
+// Captured graphs of 16, 8, 4, 2 and 1 steps for each starting state buffer:
+// a call of n steps replays at most n / 16 + 4 graphs.
+constexpr int NGRAPH = 5;
+constexpr int GRAPH_STEPS[NGRAPH] = {16, 8, 4, 2, 1};
 // Host <-> device copies of states, tracers and divergences go through a
 // staging region of the workspace in chunks of this many cells (8 doubles
 // each): no call after creation allocates device memory.
@@ -221,7 +224,7 @@ struct icr_solver {
   double cadence;
   double r_in, omega, gm, dph;
   int tile_r, variant, use_graphs, planes;
-  hipGraphExec_t g_chunk[2], g_one[2];
+  hipGraphExec_t g_steps[NGRAPH][2];
   bool graphs_ok;
   int dev;                  // HIP device the solver was created on
   double* part_override;    // non-null: stage-2 partials go here (icr_step_noalloc)
@@ -390,10 +393,8 @@ struct icr_solver {
 
   void drop_graphs() {
     if (!graphs_ok) return;
-    for (int q = 0; q < 2; ++q) {
-      (void)hipGraphExecDestroy(g_chunk[q]);
-      (void)hipGraphExecDestroy(g_one[q]);
-    }
+    for (int p = 0; p < NGRAPH; ++p)
+      for (int q = 0; q < 2; ++q) (void)hipGraphExecDestroy(g_steps[p][q]);
     graphs_ok = false;
   }
 
@@ -419,12 +420,16 @@ struct icr_solver {
 
   int build_graphs() {
     if (graphs_ok) return ICR_OK;
-    for (int q = 0; q < 2; ++q) {
-      int rc = capture(q, CHUNK, &g_chunk[q]);
-      if (rc) return rc;
-      rc = capture(q, 1, &g_one[q]);
-      if (rc) return rc;
-    }
+    for (int p = 0; p < NGRAPH; ++p)
+      for (int q = 0; q < 2; ++q) {
+        const int rc = capture(q, GRAPH_STEPS[p], &g_steps[p][q]);
+        if (rc) {  // release the graphs captured so far
+          for (int pp = 0; pp <= p; ++pp)
+            for (int qq = 0; qq < 2; ++qq)
+              if (pp < p || qq < q) (void)hipGraphExecDestroy(g_steps[pp][qq]);
+          return rc;
+        }
+      }
     graphs_ok = true;
     return ICR_OK;
   }
@@ -908,15 +913,12 @@ int icr_step(icr_solver* s, int n, double t_end_s, icr_step_info* info) {
     int rc = s->build_graphs();
     if (rc) return rc;
     int left = n;
-    while (left >= CHUNK) {
-      HIP_TRY(hipGraphLaunch(s->g_chunk[s->cur], s->stream));
-      left -= CHUNK;
-    }
-    while (left > 0) {
-      HIP_TRY(hipGraphLaunch(s->g_one[s->cur], s->stream));
-      s->cur ^= 1;
-      --left;
-    }
+    for (int p = 0; p < NGRAPH; ++p)
+      while (left >= GRAPH_STEPS[p] && (p == 0 || (left & GRAPH_STEPS[p]))) {
+        HIP_TRY(hipGraphLaunch(s->g_steps[p][s->cur], s->stream));
+        s->cur ^= GRAPH_STEPS[p] & 1;  // an even number of steps keeps the buffer
+        left -= GRAPH_STEPS[p];
+      }
   } else {
     for (int q = 0; q < n; ++q) {
       s->enqueue_step(s->cur, s->stream);

@@ -126,9 +126,10 @@ def relax_map(g: Grid, seed: int, omega: float = OMEGA_SUN) -> np.ndarray:
 
 def dynamic_maps(g: Grid, seed: int, n_maps: int = 10, cadence: float = 6 * HOUR,
                  tilt_max: float = 40 * DEG, width_var: float = 0.2,
-                 omega: float = OMEGA_SUN):
+                 omega: float = OMEGA_SUN, **wind):
     """Map sequence: tilt drifting linearly 0..tilt_max, slow-band half-width
-    15 deg * (1 + width_var * u_k), u_k ~ U[-1, 1]; fixed sheet phase.
+    15 deg * (1 + width_var * u_k), u_k ~ U[-1, 1]; fixed sheet phase; extra
+    keywords (b_r, n_fast, ...) go to wind_map.
     Returns (times [s], maps [n][8][nt][np])."""
     rng = np.random.default_rng(seed)
     phi0 = rng.uniform(0.0, 2.0 * math.pi)
@@ -136,7 +137,7 @@ def dynamic_maps(g: Grid, seed: int, n_maps: int = 10, cadence: float = 6 * HOUR
     times = np.arange(n_maps) * cadence
     maps = np.stack([
         wind_map(g, tilt_max * k / max(n_maps - 1, 1), phi0,
-                 half_width=15 * DEG * (1.0 + width_var * u[k]), omega=omega)
+                 half_width=15 * DEG * (1.0 + width_var * u[k]), omega=omega, **wind)
         for k in range(n_maps)])
     return times, maps
 
