@@ -55,12 +55,14 @@ def parse():
                          "FETCH_SIZE and WRITE_SIZE of this bench, of --copy-calibration, "
                          "then optionally one with SQ_INSTS_VALU of this bench")
     ap.add_argument("--workload", default="prod",
-                    choices=("prod", "ensemble", "relax", "jupiter", "fullrun"),
+                    choices=("prod", "ensemble", "relax", "jupiter", "fullrun", "amr"),
                     help="prod: 600x60x120 dynamic run (the headline line); ensemble: 64 "
                          "runs batched vs the same runs one after the other; relax: warm vs "
                          "plain relaxation on held-out maps; jupiter: 5.5 AU domain with "
                          "hourly maps streamed into a 4-map buffer")
     ap.add_argument("--runs", type=int, default=64)
+    ap.add_argument("--amr-levels", type=int, default=4)
+    ap.add_argument("--amr-blocks", type=int, default=40000)
     ap.add_argument("--maps", type=int, default=4, help="held-out maps for --workload relax")
     ap.add_argument("--flux", default="tvdlf", choices=("tvdlf", "hll", "hlld"),
                     help="face flux of the production run (the headline line uses tvdlf)")
@@ -293,6 +295,68 @@ def fullrun_bench(args):
     print(json.dumps({"fullrun": results}), flush=True)
 
 
+def amr_bench(args):
+    """Block-refined run (the refined runs of Sect. 3.2 / Sect. 4): base grid
+    150 x 30 x 60 in blocks of 10 x 6 x 6 cells, up to 4 levels (the finest
+    at 1200 x 240 x 480 resolution), combined criterion, regrid every 10
+    steps, the production maps and cone CME inserted from t = 10 min.  Reports
+    leaf cell-updates/s over the timed steps (regrids included) and the
+    leaves per level."""
+    import numpy as np
+    import torch
+
+    from paper_2501_15923_amd import configs
+    from paper_2501_15923_amd.amr import AmrSolver
+
+    w = configs.prod_cme(nr=150, nt=30, nph=60)
+    g = w.grid
+    s = AmrSolver(g, block=(10, 6, 6), max_level=args.amr_levels, criterion="combined",
+                  regrid_every=10, max_blocks=args.amr_blocks)
+    s.set_maps(w.times, w.maps)
+    cme = w.cmes.copy()
+    cme[0, 0] = 600.0  # the production cone CME, inserted from 10 minutes on
+    s.set_cmes(cme)
+    s.init_radial()
+    log(f"bench: AMR {g.nr}x{g.nt}x{g.np_} base, blocks 10x6x6, {args.amr_levels} levels")
+    s.step(args.warmup)
+    torch.cuda.synchronize()
+    leaves0 = s.leaves()
+    t0 = time.perf_counter()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    ev0.record()
+    cells = 0
+    chunk = 10
+    done = 0
+    while done < args.steps:
+        n = min(chunk, args.steps - done)
+        lv = s.leaves()
+        cells += len(lv) * 360 * n
+        s.step(n)
+        done += n
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1)
+    wall = time.perf_counter() - t0
+    lv = s.leaves()
+    counts = {}
+    for k in lv:
+        counts[k[0]] = counts.get(k[0], 0) + 1
+    clk = s.clock()
+    s.close()
+    out = {"metric": "MHD cell-updates/s on the refined grid (leaf cells)", "unit": "cell-updates/s",
+           "value": cells / (ms * 1e-3), "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_per_step": ms / args.steps, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"amr_{g.nr}x{g.nt}x{g.np_}_blocks10x6x6_L{args.amr_levels}",
+                      "criterion": "combined", "regrid_every": 10,
+                      "leaves_per_level_end": counts, "leaves_start": len(leaves0),
+                      "mean_leaf_cells": cells / args.steps, "simulated_h": clk["t"] / 3600,
+                      "wall_s": wall},
+           "roofline": None}
+    print(json.dumps(out), flush=True)
+
+
 def jupiter_bench(args):
     """Extended domain to 5.5 AU (803 x 60 x 120 cells), hourly maps streamed
     into a 4-map buffer while the run advances (appends inside the timed
@@ -490,6 +554,9 @@ def main():
         return
     if args.workload == "fullrun":
         fullrun_bench(args)
+        return
+    if args.workload == "amr":
+        amr_bench(args)
         return
     import numpy as np
     import torch

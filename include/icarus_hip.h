@@ -185,7 +185,7 @@ int icr_set_boundary_maps(icr_solver *s, int n_maps, const double *t_s,
                           const double *maps_si, int maps_on_device);
 
 /* Stream later maps into a run (long dynamic runs with more maps than fit,
- * e.g. an extended domain with an hourly map cadence; Sect. 3 and 5).
+ * e.g. an extended domain with an hourly map cadence; Sect. 3 and 4).
  * Appends n maps in the layout of icr_set_boundary_maps, with times strictly
  * after the last map held.  First the maps that can no longer bracket any
  * time from the clock on are dropped: those before the last map time <= t.
@@ -198,7 +198,7 @@ int icr_set_boundary_maps(icr_solver *s, int n_maps, const double *t_s,
 int icr_append_boundary_maps(icr_solver *s, int n_maps, const double *t_s,
                              const double *maps_si, int maps_on_device, int *n_held);
 
-/* Cone CMEs (Sect. 3.2 bc_icarus; Table 1 parameters): n <= max_cmes rows
+/* Cone CMEs (Sect. 3.2 bc_icarus; Table 2 parameters): n <= max_cmes rows
  * of 8 SI values: insertion start [s], duration [s], latitude [rad],
  * co-rotating longitude [rad], half-width [rad], speed [m/s], density
  * [kg/m^3], temperature [K].  While t_start <= t < t_start + duration the
@@ -378,6 +378,74 @@ int icr_ens_set_mode(icr_ensemble *e, int persistent, int grid_blocks,
  * any run produced an invalid cell (that run stops advancing, the others
  * continue). */
 int icr_ens_step(icr_ensemble *e, int n_steps, double t_end_s, icr_step_info *info);
+
+/* ------------------------------------------------------------------------
+ * Block-structured adaptive mesh refinement (Sect. 3.2 and Sect. 4: the
+ * 2015 runs refine the radially stretched grid up to five levels where the
+ * CME tracer ('tracing'), a compression or shock ('shock') or either
+ * ('combined') is present in a block).
+ *
+ * The grid of icr_grid is level 1, cut into blocks of block_r x block_theta
+ * x block_phi cells; a level-(l+1) block is one octant of a level-l block
+ * at twice the resolution in r (edges split at the geometric mean), theta
+ * and phi.  One dt for all levels (CFL over every leaf cell), SSP-RK2 on the
+ * leaves, two ghost layers per block: copies, volume-weighted restriction
+ * of finer leaves, conservative minmod-limited prolongation of the coarser
+ * leaf; the physical edges of the uniform solver (inner boundary: the map
+ * value of the base column containing a cell, the cone CME tested at the
+ * cell's own centre).  A coarse cell next to finer leaves takes their
+ * area-weighted face fluxes (mass and B_r conserved to round-off).  The
+ * passive CME tracer is always carried.  Every regrid_every steps a leaf
+ * below max_level is split when its criterion holds (max tau >=
+ * tau_threshold; max over its cells of -div(V) r / (2 |v_r|) >=
+ * shock_threshold), and 8 leaf children none of which holds it are merged;
+ * face neighbours stay within one level.  FP64; minmod or MC with TVDLF,
+ * HLL or HLLD; the map transverse rule.
+ * ------------------------------------------------------------------------ */
+enum { ICR_AMR_TRACING = 0, ICR_AMR_SHOCK = 1, ICR_AMR_COMBINED = 2 };
+
+typedef struct {
+  int block_r, block_theta, block_phi;  /* >= 4 each, dividing the grid   */
+  int max_level;                        /* 1 (no refinement) .. 6          */
+  int criterion;                        /* ICR_AMR_*                       */
+  double tau_threshold;                 /* tracing: CME mass fraction      */
+  double shock_threshold;               /* shock: dimensionless compression */
+  int regrid_every;                     /* steps between regrids, >= 1     */
+  int max_blocks;                       /* block pool over all levels      */
+} icr_amr_params;
+
+typedef struct icr_amr icr_amr;
+
+/* Device bytes of a refined run (caller-owned, as for icr_create). */
+int icr_amr_workspace_bytes(const icr_grid *grid, const icr_phys *phys,
+                            const icr_amr_params *params, size_t *bytes);
+int icr_amr_create(const icr_grid *grid, const icr_phys *phys,
+                   const icr_amr_params *params, void *dev_workspace,
+                   size_t workspace_bytes, void *hip_stream, icr_amr **out);
+void icr_amr_destroy(icr_amr *a);
+/* Boundary maps and cone CMEs: as icr_set_boundary_maps (host maps) and
+ * icr_set_cmes. */
+int icr_amr_set_boundary_maps(icr_amr *a, int n_maps, const double *t_s,
+                              const double *maps_si);
+int icr_amr_set_cmes(icr_amr *a, int n, const double *rows);
+/* Level-1 leaves from the radial expansion of the first map (Sect. 2.1),
+ * tracer 0, clock at 0, first dt. */
+int icr_amr_init_radial(icr_amr *a);
+/* n_steps RK2 steps with a regrid after every regrid_every-th step of the
+ * run; t_end_s as in icr_step.  ICR_ERR_STATE when the block pool is full,
+ * ICR_ERR_NONPHYSICAL on an invalid cell (bad_cell = slot * cells per block
+ * + cell). */
+int icr_amr_step(icr_amr *a, int n_steps, double t_end_s, icr_step_info *info);
+/* Split the given leaves (keys [n][4]: level, block index along r, theta,
+ * phi at that level) and the coarser leaves the one-level rule needs. */
+int icr_amr_force_refine(icr_amr *a, int n, const int *keys);
+/* Leaves in (level, i, j, k) order: *n receives the count, keys [cap][4]. */
+int icr_amr_leaves(icr_amr *a, int cap, int *keys, int *n);
+/* One leaf's cells, conservative in code units (the 8 variables of
+ * ICR_STATE_CONS_CODE, then rho tau): [9][block_phi][block_theta][block_r]
+ * host doubles. */
+int icr_amr_get_block(icr_amr *a, const int *key, double *out);
+int icr_amr_get_clock(icr_amr *a, icr_clock *out);
 
 #ifdef __cplusplus
 }

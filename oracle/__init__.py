@@ -80,6 +80,7 @@ def lib():
         L.orc_divv.argtypes = [P, D]
         L.orc_face_flux.argtypes = [P, D, D, ctypes.c_int, D]
         L.orc_ghosts.argtypes = [P]
+        L.orc_rhs.argtypes = [P, D, D, D, D, D]
         L.orc_threads.restype = ctypes.c_int
         L.orc_threads.argtypes = []
         L.orc_set_threads.argtypes = [ctypes.c_int]
@@ -114,7 +115,8 @@ class Oracle:
                  th_min=None, th_max=None, gamma=1.5, omega=2.87e-6, cfl=0.4,
                  flux=FLUX_TVDLF, limiter=LIM_MINMOD, gravity=True, corot=True,
                  bc_transverse=BCT_MAP, bc_mode=BCM_DRIVEN,
-                 slab_bcx=SLABX_OUTFLOW, box=(0, 1, 0, 1, 0, 1), tracer=False):
+                 slab_bcx=SLABX_OUTFLOW, box=(0, 1, 0, 1, 0, 1), tracer=False,
+                 ph_min=0.0, ph_max=2.0 * np.pi):
         from paper_2501_15923_amd import synth
         self.nr, self.nt, self.np_ = nr, nt, nph
         self.geom = geom
@@ -126,7 +128,7 @@ class Oracle:
             synth.AU * 2.0 if r_out is None else r_out,
             synth.DEG * 30 if th_min is None else th_min,
             synth.DEG * 150 if th_max is None else th_max,
-            gamma, omega, cfl, *box], dtype=np.float64)
+            gamma, omega, cfl, *box, ph_min, ph_max], dtype=np.float64)
         self._ip, self._dp = ip, dp
         self.h = lib().orc_create(ip.ctypes.data_as(ctypes.POINTER(ctypes.c_int)), _d(dp))
         if not self.h:
@@ -259,3 +261,28 @@ class Oracle:
         out = np.zeros((self.np_, self.nt, self.nr))
         lib().orc_divv(self.h, _d(out))
         return out
+
+    def rhs(self, Upad, Tpad=None):
+        """One stage's right-hand side on a caller-set padded conservative
+        state (code units, ghosts included; build with bc_mode=BCM_FROZEN):
+        (L [8][np][nt][nr], LT [np][nt][nr] or None, box-face fluxes dict
+        'r-', 'r+' [9][np][nt], 't-', 't+' [9][np][nr], 'p-', 'p+' [9][nt][nr])."""
+        Upad = np.ascontiguousarray(Upad, dtype=np.float64)
+        L = np.zeros(self.shape)
+        LT = np.zeros(self.shape[1:]) if Tpad is not None else None
+        nr, nt, nph = self.nr, self.nt, self.np_
+        sizes = [nph * nt, nph * nr, nt * nr]
+        bf = np.zeros(2 * 9 * sum(sizes))
+        tp = None
+        if Tpad is not None:
+            tp = np.ascontiguousarray(Tpad, dtype=np.float64)
+        lib().orc_rhs(self.h, _d(Upad), _d(tp) if tp is not None else None, _d(L),
+                      _d(LT) if LT is not None else None, _d(bf))
+        faces, off = {}, 0
+        shapes = [(nph, nt), (nph, nr), (nt, nr)]
+        for d, name in enumerate("rtp"):
+            for side in "-+":
+                n = 9 * sizes[d]
+                faces[name + side] = bf[off:off + n].reshape((9,) + shapes[d])
+                off += n
+        return L, LT, faces

@@ -393,7 +393,9 @@ static void build_grid(orc_ctx *c, const double *dp) {
     double t0 = dp[2], t1 = dp[3];
     for (int j = 0; j <= c->nt; ++j)
       c->te[j] = t0 + (t1 - t0) * (double)j / c->nt;
-    double p0 = 0.0, p1 = 2.0 * 3.14159265358979323846;
+    /* longitude range: the full circle (periodic), or a sub-range for a
+     * block of a refined grid whose ghosts the caller sets */
+    double p0 = dp[13], p1 = dp[14];
     for (int k = 0; k <= c->np; ++k)
       c->pe[k] = p0 + (p1 - p0) * (double)k / c->np;
   } else {
@@ -439,8 +441,9 @@ static void build_metric(orc_ctx *c) {
 }
 
 /* ip: nr nt np geom flux limiter gravity corot bc_transverse bc_mode slab_bcx
+ *     tracer
  * dp: r_in[m] r_out[m] th_min th_max gamma omega[rad/s] cfl
- *     x0 x1 y0 y1 z0 z1 (slab only, code units) */
+ *     x0 x1 y0 y1 z0 z1 (slab only, code units) ph_min ph_max (spherical) */
 void *orc_create(const int *ip, const double *dp) {
   orc_ctx *c = xcalloc(1, sizeof(orc_ctx));
   if (!c) return 0;
@@ -737,6 +740,11 @@ static void fill_ghosts(orc_ctx *c, double *U, double t) {
  * periodic in phi. */
 static void tracer_upwind(orc_ctx *c, const double *U, const double *T, double t) {
   int nr = c->nr, nt = c->nt, np = c->np;
+  if (c->bc_mode == BCM_FROZEN) { /* ghosts set by the caller: tau = T / rho */
+    size_t n = pad_cells(c);
+    for (size_t o = 0; o < n; ++o) c->P[o] = U[o] != 0.0 ? T[o] / U[o] : 0.0;
+    return;
+  }
   for (int k = 0; k < np; ++k)
     for (int j = 0; j < nt; ++j)
       for (int i = 0; i < nr; ++i)
@@ -767,8 +775,21 @@ static void tracer_upwind(orc_ctx *c, const double *U, const double *T, double t
 
 /* Right-hand side L = -div F + S of every active cell (and, with the tracer
  * on, LT = -div(F_rho tau_upwind) from the same mass fluxes). */
+/* bf (may be NULL): the face fluxes on the six faces of the active box,
+ * [9][...] per face (the 8 variables and the tracer flux), faces in the
+ * order r-low, r-high ([np][nt] each), theta-low, theta-high ([np][nr]),
+ * phi-low, phi-high ([nt][nr]). */
+static void compute_rhs_bf(orc_ctx *c, double *U, double *L, double *bnd,
+                           const double *T, double *LT, double *tbnd, double t,
+                           double *bf);
 static void compute_rhs(orc_ctx *c, double *U, double *L, double *bnd,
                         const double *T, double *LT, double *tbnd, double t) {
+  compute_rhs_bf(c, U, L, bnd, T, LT, tbnd, t, 0);
+}
+
+static void compute_rhs_bf(orc_ctx *c, double *U, double *L, double *bnd,
+                           const double *T, double *LT, double *tbnd, double t,
+                           double *bf) {
   int nr = c->nr, nt = c->nt, np = c->np;
   double gam = c->gamma;
   size_t np_cells = pad_cells(c);
@@ -848,6 +869,26 @@ static void compute_rhs(orc_ctx *c, double *U, double *L, double *bnd,
                                   : c->P[IX(c, 0, i, j, k)];
             c->FT[IX(c, 0, i, j, k)] = fm * up;
           }
+    }
+    /* the fluxes through the low and high faces of the active box */
+    if (bf) {
+      size_t off = 0, fsz[3];
+      fsz[0] = (size_t)np * nt;
+      fsz[1] = (size_t)np * nr;
+      fsz[2] = (size_t)nt * nr;
+      for (int d = 0; d < dir; ++d) off += 2 * 9 * fsz[d];
+      for (int side = 0; side < 2; ++side)
+        for (int v = 0; v < 9; ++v) {
+          double *out = bf + off + ((size_t)side * 9 + v) * fsz[dir];
+          size_t q = 0;
+          int m = side ? n : 0;
+          for (int a = 0; a < (dir == 2 ? nt : np); ++a)
+            for (int b = 0; b < (dir == 0 ? nt : nr); ++b, ++q) {
+              int i = dir == 0 ? m : b, j = dir == 0 ? b : (dir == 1 ? m : a);
+              int k = dir == 2 ? m : a;
+              out[q] = v < 8 ? F[IX(c, v, i, j, k)] : (T ? c->FT[IX(c, 0, i, j, k)] : 0.0);
+            }
+        }
     }
     /* divergence of the face fluxes, face m-1/2 stored at index m */
 #pragma omp parallel for
@@ -1480,4 +1521,31 @@ void orc_divb(void *h, double *out) {
 int orc_threads(void) { return omp_get_max_threads(); }
 void orc_set_threads(int n) {
   if (n > 0) omp_set_num_threads(n);
+}
+
+/* Right-hand side of one stage on a caller-set padded state (ghost layers
+ * included, bc_mode frozen): L = -div F + S of every active cell, [8][np][nt][nr]
+ * in code units (LT, the tracer's, [np][nt][nr], when the oracle carries the
+ * tracer and T is given), and the fluxes through the six faces of the active
+ * box (layout of compute_rhs_bf).  A block of a refined grid is stepped by
+ * calling this on its padded state and combining the stages outside. */
+int orc_rhs(void *h, const double *Upad, const double *Tpad, double *L_out,
+            double *LT_out, double *bf) {
+  orc_ctx *c = h;
+  int nr = c->nr, nt = c->nt, np = c->np;
+  size_t n = pad_cells(c);
+  double bnd[NV], tb = 0.0;
+  memcpy(c->U0, Upad, n * NV * sizeof(double));
+  int trc = c->tracer && Tpad;
+  if (trc) memcpy(c->T0, Tpad, n * sizeof(double));
+  compute_rhs_bf(c, c->U0, c->L, bnd, trc ? c->T0 : 0, c->LT, &tb, c->t, bf);
+  size_t act = (size_t)nr * nt * np;
+  for (int k = 0; k < np; ++k)
+    for (int j = 0; j < nt; ++j)
+      for (int i = 0; i < nr; ++i) {
+        size_t q = ((size_t)k * nt + j) * nr + i;
+        for (int v = 0; v < NV; ++v) L_out[v * act + q] = c->L[IX(c, v, i, j, k)];
+        if (trc && LT_out) LT_out[q] = c->LT[IX(c, 0, i, j, k)];
+      }
+  return 0;
 }

@@ -32,6 +32,14 @@ class IcrPhys(ctypes.Structure):
                 ("bc_transverse", ctypes.c_int)]
 
 
+class IcrAmrParams(ctypes.Structure):
+    _fields_ = [("block_r", ctypes.c_int), ("block_theta", ctypes.c_int),
+                ("block_phi", ctypes.c_int), ("max_level", ctypes.c_int),
+                ("criterion", ctypes.c_int), ("tau_threshold", ctypes.c_double),
+                ("shock_threshold", ctypes.c_double), ("regrid_every", ctypes.c_int),
+                ("max_blocks", ctypes.c_int)]
+
+
 class IcrClock(ctypes.Structure):
     _fields_ = [("t", ctypes.c_double), ("step", ctypes.c_longlong),
                 ("last_dt", ctypes.c_double), ("next_dt", ctypes.c_double),
@@ -102,6 +110,20 @@ SIGNATURES = {
     "icr_get_tracer": (I, [P, D, I]),
     "icr_divv": (I, [P, D, I]),
     "icr_sample_shell": (I, [P, ctypes.c_double, D]),
+    "icr_amr_workspace_bytes": (I, [ctypes.POINTER(IcrGrid), ctypes.POINTER(IcrPhys),
+                                    ctypes.POINTER(IcrAmrParams), ctypes.POINTER(ctypes.c_size_t)]),
+    "icr_amr_create": (I, [ctypes.POINTER(IcrGrid), ctypes.POINTER(IcrPhys),
+                           ctypes.POINTER(IcrAmrParams), P, ctypes.c_size_t, P,
+                           ctypes.POINTER(P)]),
+    "icr_amr_destroy": (None, [P]),
+    "icr_amr_set_boundary_maps": (I, [P, I, D, D]),
+    "icr_amr_set_cmes": (I, [P, I, D]),
+    "icr_amr_init_radial": (I, [P]),
+    "icr_amr_step": (I, [P, I, ctypes.c_double, ctypes.POINTER(IcrStepInfo)]),
+    "icr_amr_force_refine": (I, [P, I, ctypes.POINTER(ctypes.c_int)]),
+    "icr_amr_leaves": (I, [P, I, ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_int)]),
+    "icr_amr_get_block": (I, [P, ctypes.POINTER(ctypes.c_int), D]),
+    "icr_amr_get_clock": (I, [P, ctypes.POINTER(IcrClock)]),
     # warm-start network (include/icarus_nn.h)
     "icr_nn_last_error": (ctypes.c_char_p, []),
     "icr_nn_param_count": (I, [ctypes.POINTER(NnShape), ctypes.POINTER(ctypes.c_longlong)]),

@@ -17,7 +17,7 @@ LIB = os.path.join(PKG, "libicarus_hip.so")
 OBJ_DIR = os.path.join(PKG, "_build")
 SOURCES = [os.path.join(PKG, "csrc", f)
            for f in ("icr_kernels.hip", "icr_stage_lds.hip", "icr_ensemble.hip", "icr_api.hip",
-                     "icr_nn.hip")]
+                     "icr_nn.hip", "icr_amr.hip")]
 HEADERS = [os.path.join(PKG, "csrc", f) for f in ("icr_kernels.hpp", "icr_device.hpp")] + \
     [os.path.join(ROOT, "include", "icarus_hip.h")]
 

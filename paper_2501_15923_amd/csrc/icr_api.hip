@@ -208,6 +208,15 @@ int scratch_for_device(int dev, double** out) {
 
 }  // namespace
 
+namespace icr {
+// The error channel of icr_last_error(), for the other host translation
+// units of the library.
+int set_error(int code, const char* msg) {
+  g_err = msg;
+  return code;
+}
+}  // namespace icr
+
 struct icr_solver {
   icr_grid g;
   icr_phys p;

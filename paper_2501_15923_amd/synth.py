@@ -3,7 +3,7 @@ cone-CME parameters, all in SI units.
 
 These stand in for the coronal-model boundary files, trajectory files and CME
 catalogue entries that drive the heliospheric model (Icarus 3.0, Sect. 2.1
-boundary data, Sect. 2 trajectory files, Sect. 3.2 Table 1 cone CMEs).  The
+boundary data, Sect. 2 trajectory files, Sect. 3.2 Table 2 cone CMEs).  The
 module only *produces input data*; it holds no part of the MHD update, and
 both the HIP library and the CPU oracle read its output.
 

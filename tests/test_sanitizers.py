@@ -38,6 +38,15 @@ for flux, lim, bct, trc in ((0, 0, 0, True), (1, 1, 1, False), (2, 2, 0, False),
     if trc:
         o.set_tracer(0.5); o.get_tracer(); o.tracer_flux()
     o.get_state(kind=2); o.get_state(kind=0); o.last_boundary_flux(); o.dt()
+from oracle.amr import AmrConfig, AmrOracle
+ga = synth.Grid(16, 8, 8)
+a = AmrOracle(AmrConfig(ga.nr, ga.nt, ga.np_, ga.r_in, ga.r_out, ga.th_min, ga.th_max,
+                        max_level=2, regrid_every=1))
+a.set_maps(*synth.dynamic_maps(ga, 2, cadence=600.0))
+a.set_cmes(cme)
+a.init_radial()
+a.force_refine([(1, 0, 0, 0)])
+a.step(2)
 s = oracle.Oracle(16, 1, 1, geom=oracle.GEOM_SLAB, gravity=False, corot=False, box=(0, 1, 0, 1, 0, 1))
 W = np.zeros(s.shape); W[0] = 1.0; W[4] = 1.0; W[5] = 0.3
 s.set_state(W, kind=3); s.step(10)
@@ -99,6 +108,25 @@ assert L.icr_nn_workspace_bytes(B(shape), B(n)) == 0
 bad = _abi.NnShape(60, 120, 600, 64, 128, 384, 8, 5, 46)
 assert L.icr_nn_param_count(B(bad), B(cnt)) == -1
 L.icr_nn_last_error()
+q = lambda **kw: _abi.IcrAmrParams(**dict(dict(block_r=10, block_theta=6, block_phi=6,
+                                               max_level=3, criterion=2, tau_threshold=0.05,
+                                               shock_threshold=0.5, regrid_every=5,
+                                               max_blocks=4000), **kw))
+ag = grid(n_r=150, n_theta=30, n_phi=60)
+for g, p, qq, want in [(ag, phys(), q(), 0), (ag, phys(precision=32), q(), -5),
+                       (ag, phys(limiter=2), q(), -5), (ag, phys(), q(block_r=7), -1),
+                       (ag, phys(), q(max_level=7), -1), (ag, phys(), q(max_blocks=10), -1),
+                       (ag, phys(), q(criterion=3), -1), (ag, phys(), q(regrid_every=0), -1),
+                       (ag, phys(bc_transverse=1), q(), -5), (grid(), phys(), q(), -1)]:
+    assert L.icr_amr_workspace_bytes(B(g), B(p), B(qq), B(n)) == want, (qq.block_r, want)
+    L.icr_last_error()
+assert L.icr_amr_create(B(ag), B(phys()), B(q()), None, 0, None, B(h)) == -1
+I = ctypes.POINTER(ctypes.c_int)
+for name, args in [("icr_amr_init_radial", ()), ("icr_amr_step", (1, -1.0, None)),
+                   ("icr_amr_force_refine", (0, None)), ("icr_amr_leaves", (0, None, None)),
+                   ("icr_amr_get_block", (None, None)), ("icr_amr_get_clock", (None,)),
+                   ("icr_amr_set_cmes", (0, None)), ("icr_amr_set_boundary_maps", (1, None, None))]:
+    assert getattr(L, name)(None, *args) == -1, name
 print("host ok")
 """
 
@@ -138,17 +166,20 @@ def test_host_library_under_address_sanitizer(tmp_path):
     if not rt:
         pytest.skip("no clang ASan runtime")
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    api_o = str(tmp_path / "icr_api_asan.o")
     lib = str(tmp_path / "libicarus_asan.so")
     # host code instrumented, device code as in the product build
-    subprocess.check_call([hipcc, "--offload-arch=gfx950", "-O1", "-g", "-std=c++17", "-fPIC",
-                           "-ffp-contract=on", "-Xclang", "-target-feature", "-Xclang",
-                           "-packed-fp32-ops", "-Xarch_host", "-fsanitize=address",
-                           "-Xarch_host", "-fno-omit-frame-pointer",
-                           "-I" + os.path.join(ROOT, "include"), "-c", "-o", api_o,
-                           os.path.join(PKG, "csrc", "icr_api.hip")],
-                          stderr=subprocess.DEVNULL)
+    inst = []
+    for src in ("icr_api", "icr_amr"):
+        o = str(tmp_path / (src + "_asan.o"))
+        subprocess.check_call([hipcc, "--offload-arch=gfx950", "-O1", "-g", "-std=c++17",
+                               "-fPIC", "-ffp-contract=on", "-Xclang", "-target-feature",
+                               "-Xclang", "-packed-fp32-ops", "-Xarch_host",
+                               "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer",
+                               "-I" + os.path.join(ROOT, "include"), "-c", "-o", o,
+                               os.path.join(PKG, "csrc", src + ".hip")],
+                              stderr=subprocess.DEVNULL)
+        inst.append(o)
     subprocess.check_call([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-Xarch_host",
                            "-fsanitize=address", "-Xarch_host", "-shared-libasan", "-o", lib,
-                           api_o, *objs])
+                           *inst, *objs])
     assert "host ok" in _run(HOST_SCRIPT, lib, rt[-1])
