@@ -439,7 +439,8 @@ int icr_amr_step(icr_amr *a, int n_steps, double t_end_s, icr_step_info *info);
 /* Split the given leaves (keys [n][4]: level, block index along r, theta,
  * phi at that level) and the coarser leaves the one-level rule needs. */
 int icr_amr_force_refine(icr_amr *a, int n, const int *keys);
-/* Leaves in (level, i, j, k) order: *n receives the count, keys [cap][4]. */
+/* Leaves in (level, i, j, k) order: *n receives the count, keys [cap][4]
+ * receives the first cap of them (cap = 0: the count only, keys may be NULL). */
 int icr_amr_leaves(icr_amr *a, int cap, int *keys, int *n);
 /* One leaf's cells, conservative in code units (the 8 variables of
  * ICR_STATE_CONS_CODE, then rho tau): [9][block_phi][block_theta][block_r]

@@ -85,7 +85,12 @@ class AmrSolver:
         check(lib().icr_amr_leaves(self.h, self.max_blocks,
                                    keys.ctypes.data_as(ctypes.POINTER(ctypes.c_int)),
                                    ctypes.byref(n)))
-        return [tuple(int(x) for x in r) for r in keys[:n.value]]
+        return [tuple(r) for r in keys[:n.value].tolist()]
+
+    def n_leaves(self):
+        n = ctypes.c_int()
+        check(lib().icr_amr_leaves(self.h, 0, None, ctypes.byref(n)))
+        return n.value
 
     def block(self, key):
         br, bt, bp = self.bshape

@@ -384,26 +384,24 @@ __global__ void __launch_bounds__(256) k_amr_stage(AmrArgs a, const int* __restr
 }
 
 // --------------------------------------------------------- flux correction --
-// One thread per (listed coarse leaf, face of direction d, face cell): where
-// the face's neighbour region holds finer leaves, replace the coarse face's
-// A F by the sum of the fine faces' A F.  coef: 1 after stage 1 (U1), 1/2
-// after stage 2 (U).  An edge or corner cell of a block lies on faces of
-// several directions: one launch per direction keeps each cell's updates
-// ordered (blocks have >= 4 cells a side, so the two faces of one direction
-// never share a cell).
+// One thread per (listed face of direction d, face cell): the list holds
+// 2 slot + side of the coarse leaf faces whose neighbour region holds finer
+// leaves; the coarse face's A F is replaced by the sum of the fine faces'
+// A F.  coef: 1 after stage 1 (U1), 1/2 after stage 2 (U).  An edge or
+// corner cell of a block lies on faces of several directions: one launch
+// per direction keeps each cell's updates ordered (blocks have >= 4 cells a
+// side, so the two faces of one direction never share a cell).
 __global__ void __launch_bounds__(256) k_amr_reflux(AmrArgs a, const int* __restrict__ list,
                                                     int n, int stage, int d) {
-  const int per = 2 * face_cells(a, d);
+  const int area = face_cells(a, d);
   const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= (long long)per * n || !a.clock->active) return;
-  const int slot = list[q / per];
-  const int r = (int)(q % per);
+  if (q >= (long long)area * n || !a.clock->active) return;
+  const int ent = list[q / area];
+  const int slot = ent >> 1, side = ent & 1;
+  const int fq = (int)(q % area);
   const int* key = a.key + 4 * slot;
   const int l = key[0];
   if (l >= a.nlev) return;
-  const int area = face_cells(a, d);
-  const int side = r / area;
-  const int fq = r - side * area;
   const int w2 = d == 0 ? a.bt : a.br;
   const int y = fq / w2, x = fq - y * w2;
   // the neighbour block of the same level across this face
@@ -446,48 +444,55 @@ __global__ void __launch_bounds__(256) k_amr_reflux(AmrArgs a, const int* __rest
   const double dt = a.clock->dt * (stage == 1 ? 1.0 : 0.5);
   double* tgt = stage == 1 ? a.U1 : a.U;
   const int gk = key[3] * a.bp + ck;
+  // the 2 x 2 fine faces: slot, face cell and area (s = 2 s2 + s1)
+  const AmrLevel& LF = a.lv[l + 1];
+  int fsl[4], fqf[4];
+  double Af[4];
+  bool ok = true;
+  for (int s = 0; s < 4; ++s) {
+    const int s2 = s >> 1, s1 = s & 1;
+    // fine cell indices (global, level l+1) on the fine side of the face
+    int fi = 2 * gi, fj = 2 * gj, fk = 2 * gk;
+    if (d == 0) {
+      fi = side ? 2 * gi + 2 : 2 * gi - 1;
+      fj += s1;
+      fk += s2;
+    } else if (d == 1) {
+      fj = side ? 2 * gj + 2 : 2 * gj - 1;
+      fi += s1;
+      fk += s2;
+    } else {
+      fk = side ? 2 * gk + 2 : 2 * gk - 1;
+      fi += s1;
+      fj += s2;
+    }
+    if (d == 2) fk = (fk + LF.np) % LF.np;
+    const int fs = amr_slot(a, l + 1, fi, fj, fk);
+    fsl[s] = fs;
+    fqf[s] = 0;
+    Af[s] = 0.0;
+    if (fs < 0) {  // cannot happen in a valid tree: poison the cell
+      ok = false;
+      continue;
+    }
+    const int* fkey = a.key + 4 * fs;
+    const int li = fi - fkey[1] * a.br, lj = fj - fkey[2] * a.bt, lk = fk - fkey[3] * a.bp;
+    if (d == 0) {
+      fqf[s] = lk * a.bt + lj;
+      Af[s] = (side ? mf.rm2[fi] : mf.rp2[fi]) / mf.ict[fj] * LF.dph;
+    } else if (d == 1) {
+      fqf[s] = lk * a.br + li;
+      Af[s] = (side ? mf.sm[fj] : mf.sp[fj]) * mf.hr[fi] / mf.ivr[fi] * LF.dph;
+    } else {
+      fqf[s] = lj * a.br + li;
+      Af[s] = mf.hr[fi] / mf.ivr[fi] * LF.dth;
+    }
+  }
   for (int v = 0; v < NA; ++v) {
     double sumf = 0.0;
-    for (int s2 = 0; s2 < 2; ++s2)
-      for (int s1 = 0; s1 < 2; ++s1) {
-        // fine cell indices (global, level l+1) on the fine side of the face
-        int fi = 2 * gi, fj = 2 * gj, fk = 2 * gk;
-        if (d == 0) {
-          fi = side ? 2 * gi + 2 : 2 * gi - 1;
-          fj += s1;
-          fk += s2;
-        } else if (d == 1) {
-          fj = side ? 2 * gj + 2 : 2 * gj - 1;
-          fi += s1;
-          fk += s2;
-        } else {
-          fk = side ? 2 * gk + 2 : 2 * gk - 1;
-          fi += s1;
-          fj += s2;
-        }
-        const AmrLevel& LF = a.lv[l + 1];
-        if (d == 2) fk = (fk + LF.np) % LF.np;
-        const int fs = amr_slot(a, l + 1, fi, fj, fk);
-        if (fs < 0) {  // cannot happen in a valid tree: poison the cell
-          sumf = __builtin_nan("");
-          continue;
-        }
-        const int* fkey = a.key + 4 * fs;
-        const int li = fi - fkey[1] * a.br, lj = fj - fkey[2] * a.bt, lk = fk - fkey[3] * a.bp;
-        int fqf;
-        double Af;
-        if (d == 0) {
-          fqf = lk * a.bt + lj;
-          Af = (side ? mf.rm2[fi] : mf.rp2[fi]) / mf.ict[fj] * LF.dph;
-        } else if (d == 1) {
-          fqf = lk * a.br + li;
-          Af = (side ? mf.sm[fj] : mf.sp[fj]) * mf.hr[fi] / mf.ivr[fi] * LF.dph;
-        } else {
-          fqf = lj * a.br + li;
-          Af = mf.hr[fi] / mf.ivr[fi] * LF.dth;
-        }
-        sumf += Af * a.F[fidx(a, fs, fface, v, fqf)];
-      }
+    for (int s = 0; s < 4; ++s)
+      if (fsl[s] >= 0) sumf += Af[s] * a.F[fidx(a, fsl[s], fface, v, fqf[s])];
+    if (!ok) sumf = __builtin_nan("");
     const double delta = sumf - Ac * a.F[fidx(a, slot, face, v, fq)];
     const double dL = (side ? -delta : delta) / V;
     tgt[pidx(a, slot, v, AG + ck, AG + cj, AG + ci)] += dt * dL;
@@ -704,7 +709,7 @@ int err(int code, const std::string& m) { return set_error(code, m.c_str()); }
 
 struct AmrLayout {
   size_t U, U1, F, leaf, key, maps[AMR_MAXL + 1], m64[AMR_MAXL + 1], mr[AMR_MAXL + 1],
-      bmaps, tau, cme, clock, partials, ind, lists, stage, total;
+      bmaps, tau, cme, clock, partials, ind, lists, rlist, stage, total;
 };
 
 }  // namespace
@@ -724,6 +729,7 @@ struct icr_amr {
   std::map<Key, int> slot_of;      // every block (leaf or not) -> slot
   std::vector<Key> key_of;         // slot -> key
   std::vector<unsigned char> leaf; // slot -> leaf flag
+  std::vector<int> hmap[AMR_MAXL + 1];  // level -> [nbp][nbt][nbr] slot or -1 (device copy: maps)
   std::vector<int> free_slots;
   int n_maps = 0, n_cme = 0;
   std::vector<double> tau_h;
@@ -794,8 +800,21 @@ struct icr_amr {
       if (leaf[kv.second] && (l == 0 || kv.first.l == l)) out.push_back(kv.first);
     return out;  // std::map order: level, i, j, k
   }
-  bool has(const Key& k) const { return slot_of.count(k) != 0; }
-  bool is_leaf(const Key& k) const { return has(k) && leaf[slot_of.at(k)]; }
+  size_t map_index(const Key& k) const {
+    return ((size_t)k.k * nb[k.l][1] + k.j) * nb[k.l][0] + k.i;
+  }
+  // slot of a block, -1 where there is none (also outside the levels / grid)
+  int slot(const Key& k) const {
+    if (k.l < 1 || k.l > nlev || k.i < 0 || k.j < 0 || k.k < 0 || k.i >= nb[k.l][0] ||
+        k.j >= nb[k.l][1] || k.k >= nb[k.l][2])
+      return -1;
+    return hmap[k.l][map_index(k)];
+  }
+  bool has(const Key& k) const { return slot(k) >= 0; }
+  bool is_leaf(const Key& k) const {
+    const int s = slot(k);
+    return s >= 0 && leaf[s];
+  }
   bool neighbour(const Key& k, int d, int side, Key* out) const {
     int b[3] = {k.i, k.j, k.k};
     b[d] += side ? 1 : -1;
@@ -821,6 +840,7 @@ struct icr_amr {
     const int s = free_slots.back();
     free_slots.pop_back();
     slot_of[k] = s;
+    hmap[k.l][map_index(k)] = s;
     key_of[s] = k;
     leaf[s] = 1;
     return s;
@@ -828,6 +848,7 @@ struct icr_amr {
   void remove_block(const Key& k) {
     const int s = slot_of.at(k);
     slot_of.erase(k);
+    hmap[k.l][map_index(k)] = -1;
     leaf[s] = 0;
     free_slots.push_back(s);
   }
@@ -846,15 +867,9 @@ struct icr_amr {
     AMR_TRY(hipMemcpyAsync(at(L.key), keys.data(), keys.size() * sizeof(int),
                            hipMemcpyHostToDevice, stream));
     AMR_TRY(hipMemcpyAsync(at(L.leaf), leaf.data(), leaf.size(), hipMemcpyHostToDevice, stream));
-    for (int l = 1; l <= nlev; ++l) {
-      const size_t n = (size_t)nb[l][0] * nb[l][1] * nb[l][2];
-      std::vector<int> m(n, -1);
-      for (const auto& kv : slot_of)
-        if (kv.first.l == l)
-          m[((size_t)kv.first.k * nb[l][1] + kv.first.j) * nb[l][0] + kv.first.i] = kv.second;
-      AMR_TRY(hipMemcpyAsync(at(L.maps[l]), m.data(), n * sizeof(int), hipMemcpyHostToDevice,
-                             stream));
-    }
+    for (int l = 1; l <= nlev; ++l)
+      AMR_TRY(hipMemcpyAsync(at(L.maps[l]), hmap[l].data(), hmap[l].size() * sizeof(int),
+                             hipMemcpyHostToDevice, stream));
     AMR_TRY(hipStreamSynchronize(stream));
     return ICR_OK;
   }
@@ -884,12 +899,32 @@ struct icr_amr {
     if (!per.empty())
       AMR_TRY(hipMemcpy(list_at(q.max_blocks), per.data(), per.size() * sizeof(int),
                         hipMemcpyHostToDevice));
+    // faces of leaves below the top level whose same-level neighbour is
+    // refined (its children there are leaves, by the one-level rule)
+    for (int d = 0; d < 3; ++d) {
+      std::vector<int> e;
+      for (const int sl : all) {
+        const Key& k = key_of[sl];
+        if (k.l >= nlev) continue;
+        for (int side = 0; side < 2; ++side) {
+          Key nk;
+          if (!neighbour(k, d, side, &nk)) continue;
+          const int ns = slot(nk);
+          if (ns >= 0 && !leaf[ns]) e.push_back(2 * sl + side);
+        }
+      }
+      n_rl[d] = (int)e.size();
+      if (!e.empty())
+        AMR_TRY(hipMemcpy(rlist_at(d), e.data(), e.size() * sizeof(int), hipMemcpyHostToDevice));
+    }
     return ICR_OK;
   }
+  int n_rl[3] = {0, 0, 0};
+  int* rlist_at(int d) { return (int*)at(L.rlist) + (size_t)d * 2 * q.max_blocks; }
 
   std::vector<int> slots(const std::vector<Key>& ks) const {
     std::vector<int> s;
-    for (const Key& k : ks) s.push_back(slot_of.at(k));
+    for (const Key& k : ks) s.push_back(slot(k));
     return s;
   }
 
@@ -911,16 +946,18 @@ struct icr_amr {
   void enqueue_step() {
     const size_t nl = (size_t)n_all;
     int* d_all = list_at(0);
-    const long long rper[3] = {2LL * q.block_phi * q.block_theta, 2LL * q.block_phi * q.block_r,
-                               2LL * q.block_theta * q.block_r};
+    const long long area[3] = {(long long)q.block_phi * q.block_theta,
+                               (long long)q.block_phi * q.block_r,
+                               (long long)q.block_theta * q.block_r};
     for (int stage = 1; stage <= 2; ++stage) {
       fill_ghosts_at(stage == 2, stage == 2, 0);
       AmrArgs a = args();
       launch_stage(a, d_all, (int)nl, stage);
       for (int d = 0; d < 3; ++d) {
-        const long long n = rper[d] * (long long)nl;
+        if (n_rl[d] == 0) continue;
+        const long long n = area[d] * (long long)n_rl[d];
         hipLaunchKernelGGL(k_amr_reflux, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream,
-                           a, d_all, (int)nl, stage, d);
+                           a, rlist_at(d), n_rl[d], stage, d);
       }
     }
     AmrArgs a = args();
@@ -1044,15 +1081,16 @@ struct icr_amr {
     AMR_TRY(hipMemcpyAsync(h.data(), ind, h.size() * sizeof(double), hipMemcpyDeviceToHost,
                            stream));
     AMR_TRY(hipStreamSynchronize(stream));
-    std::map<Key, bool> flag;
+    // per slot: -1 not a leaf of this regrid, else the leaf's criterion
+    std::vector<signed char> flag(q.max_blocks, -1);
+    std::set<Key> refine;
     for (size_t n = 0; n < lv.size(); ++n) {
       const bool tr = h[2 * n] >= q.tau_threshold;
       const bool sh = h[2 * n + 1] >= q.shock_threshold;
-      flag[lv[n]] = q.criterion == ICR_AMR_TRACING ? tr : (q.criterion == ICR_AMR_SHOCK ? sh : (tr || sh));
+      const bool f = q.criterion == ICR_AMR_TRACING ? tr : (q.criterion == ICR_AMR_SHOCK ? sh : (tr || sh));
+      flag[slot(lv[n])] = f ? 1 : 0;
+      if (f && lv[n].l < nlev) refine.insert(lv[n]);
     }
-    std::set<Key> refine;
-    for (const auto& kv : flag)
-      if (kv.second && kv.first.l < nlev) refine.insert(kv.first);
     balance(refine);
     std::set<Key> coarsen;
     std::set<Key> parents;
@@ -1061,8 +1099,8 @@ struct icr_amr {
     for (const Key& pk : parents) {
       bool all = true;
       for (const Key& c : children(pk)) {
-        auto it = flag.find(c);
-        if (!is_leaf(c) || it == flag.end() || it->second || refine.count(c)) all = false;
+        const int cs = slot(c);
+        if (cs < 0 || !leaf[cs] || flag[cs] != 0 || refine.count(c)) all = false;
       }
       if (!all) continue;
       bool ok = true;
@@ -1144,6 +1182,9 @@ AmrLayout amr_layout(const icr_grid& g, const icr_amr_params& q) {
   L.ind = take(sizeof(double) * 2 * mb);
   // device lists: all leaves [mb], per-level leaves [mb], temporary [4 mb]
   L.lists = take(sizeof(int) * 6 * mb);
+  // flux-correction lists: per direction, (slot, side) of the coarse leaf
+  // faces next to finer leaves [2 mb] each
+  L.rlist = take(sizeof(int) * 6 * mb);
   L.stage = take(sizeof(double) * NA * (size_t)q.block_r * q.block_theta * q.block_phi);
   L.total = off;
   return L;
@@ -1212,6 +1253,8 @@ int icr_amr_create(const icr_grid* g, const icr_phys* p, const icr_amr_params* q
     m.m64 = (double*)a->at(L.m64[l]);
     launch_metric(m, a->at(L.mr[l]), false, a->stream);
   }
+  for (int l = 1; l <= a->nlev; ++l)
+    a->hmap[l].assign((size_t)a->nb[l][0] * a->nb[l][1] * a->nb[l][2], -1);
   a->key_of.assign(q->max_blocks, Key{0, 0, 0, 0});
   a->leaf.assign(q->max_blocks, 0);
   for (int s = q->max_blocks - 1; s >= 0; --s) a->free_slots.push_back(s);

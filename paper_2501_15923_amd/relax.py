@@ -23,9 +23,17 @@ def slow_crossing_time(grid, v_slow=350e3):
 
 
 def shell_errors(shell, ref):
-    """L2-relative errors of rho and v_r on the shell."""
+    """L2-relative errors of rho and v_r on the shell (the convergence
+    criterion: the shell as a whole within the tolerance)."""
     return (float(np.linalg.norm(shell[0] - ref[0]) / np.linalg.norm(ref[0])),
             float(np.linalg.norm(shell[1] - ref[1]) / np.linalg.norm(ref[1])))
+
+
+def shell_max_errors(shell, ref):
+    """Largest pointwise relative errors of rho and v_r on the shell (a
+    stricter reading of the criterion, recorded beside the L2 one)."""
+    return (float(np.max(np.abs(shell[0] - ref[0]) / np.abs(ref[0]))),
+            float(np.max(np.abs(shell[1] - ref[1]) / np.abs(ref[1]))))
 
 
 def _sync():
@@ -91,4 +99,5 @@ def relax(solver, ref_shell, t_max, chunk=100, r_shell=AU, tol_resid=1e-4, tol_s
         out = first_relaxed(rec[-1:], tol_resid, tol_shell)
         if out["converged"] or info["steps"] < chunk or steps >= max_steps:
             out["history"] = rec
+            out["err_rho_max"], out["err_vr_max"] = shell_max_errors(sh, ref_shell)
             return out

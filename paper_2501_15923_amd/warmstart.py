@@ -234,7 +234,11 @@ def summarise(rows, names):
                          plain_steps_median=float(np.median([r["plain"]["steps"] for r in good])),
                          steps_median=float(np.median([r[name]["steps"] for r in good])),
                          err_rho_median=float(np.median([r[name]["err_rho"] for r in good])),
-                         err_vr_median=float(np.median([r[name]["err_vr"] for r in good])))
+                         err_vr_median=float(np.median([r[name]["err_vr"] for r in good])),
+                         err_rho_max_median=float(np.median([r[name].get("err_rho_max", np.nan)
+                                                             for r in good])),
+                         err_vr_max_median=float(np.median([r[name].get("err_vr_max", np.nan)
+                                                            for r in good])))
     return out
 
 
