@@ -441,28 +441,72 @@ __device__ __forceinline__ void face_flux(const R (&wl)[NV], const R (&wr)[NV],
 // g = -GM/r^2 e_r (momentum rho g, energy rho v.g); co-rotating frame with
 // Omega along the polar axis: F = rho (Omega x r) x Omega + 2 rho v x Omega
 // and energy source v.F.
+//
+// The metric factors of the cell come through an accessor: CellMetric reads
+// the global arrays at (i, j); the face-once stage kernel passes one that
+// reads its tile's copy in LDS (the same values).
+enum MetricR { MR_RM2, MR_RP2, MR_IVR, MR_HR, MR_GR, MR_IRC, MR_GRAV, MR_IDR, MR_RC, MR_N };
+enum MetricT { MT_SM, MT_SP, MT_ICT, MT_COT, MT_SNC, MT_CSC, MT_PHF, MT_ILPH, MT_N };
+
 template <typename R>
-__device__ __forceinline__ void add_sources(const R (&w)[NV], const Metric<R>& m, int i, int j,
-                                            R omega, int gravity, int corot, R (&L)[NV]) {
+__device__ __forceinline__ const R* metric_r(const Metric<R>& m, int a) {
+  switch (a) {
+    case MR_RM2: return m.rm2;
+    case MR_RP2: return m.rp2;
+    case MR_IVR: return m.ivr;
+    case MR_HR: return m.hr;
+    case MR_GR: return m.gr;
+    case MR_IRC: return m.irc;
+    case MR_GRAV: return m.grav;
+    case MR_IDR: return m.idr;
+    default: return m.rc;
+  }
+}
+template <typename R>
+__device__ __forceinline__ const R* metric_t(const Metric<R>& m, int a) {
+  switch (a) {
+    case MT_SM: return m.sm;
+    case MT_SP: return m.sp;
+    case MT_ICT: return m.ict;
+    case MT_COT: return m.cot;
+    case MT_SNC: return m.snc;
+    case MT_CSC: return m.csc;
+    case MT_PHF: return m.phf;
+    default: return m.ilph;
+  }
+}
+
+template <typename R>
+struct CellMetric {
+  const Metric<R>& m;
+  int i, j;
+  __device__ __forceinline__ R r(int a) const { return ldg(metric_r(m, a), (unsigned)i); }
+  __device__ __forceinline__ R t(int a) const { return ldg(metric_t(m, a), (unsigned)j); }
+  __device__ __forceinline__ R ilth() const { return m.ilth; }
+};
+
+template <typename R, typename CM>
+__device__ __forceinline__ void add_sources_cm(const R (&w)[NV], const CM& cm, R omega,
+                                               int gravity, int corot, R (&L)[NV]) {
   const R rho = w[0], vr = w[1], vt = w[2], vp = w[3], p = w[4];
   const R br = w[5], bt = w[6], bp = w[7];
-  const R irc = ldg(m.irc, i);
-  const R cot = ldg(m.cot, j);
+  const R irc = cm.r(MR_IRC);
+  const R cot = cm.t(MT_COT);
   const R ptot = p + R(0.5) * (br * br + bt * bt + bp * bp);
-  L[1] += (rho * (vt * vt + vp * vp) - (bt * bt + bp * bp)) * irc + ptot * ldg(m.gr, i);
+  L[1] += (rho * (vt * vt + vp * vp) - (bt * bt + bp * bp)) * irc + ptot * cm.r(MR_GR);
   L[2] += (-(rho * vr * vt - br * bt) + cot * (rho * vp * vp - bp * bp)) * irc +
-          ptot * ldg(m.hr, i) * cot;
+          ptot * cm.r(MR_HR) * cot;
   L[3] -= ((rho * vp * vr - bp * br) + cot * (rho * vp * vt - bp * bt)) * irc;
   L[6] += (vr * bt - vt * br) * irc;
   L[7] += ((vr * bp - vp * br) + cot * (vt * bp - vp * bt)) * irc;
   if (gravity) {
-    const R g = ldg(m.grav, i);
+    const R g = cm.r(MR_GRAV);
     L[1] += rho * g;
     L[4] += rho * vr * g;
   }
   if (corot) {
-    const R sn = ldg(m.snc, j), cs = ldg(m.csc, j);
-    const R r = ldg(m.rc, i);
+    const R sn = cm.t(MT_SNC), cs = cm.t(MT_CSC);
+    const R r = cm.r(MR_RC);
     const R cen = rho * omega * omega * r * sn;
     const R cor = R(2) * rho * omega;
     L[1] += cen * sn + cor * vp * sn;
@@ -470,6 +514,12 @@ __device__ __forceinline__ void add_sources(const R (&w)[NV], const Metric<R>& m
     L[3] -= cor * (vr * sn + vt * cs);
     L[4] += cen * (vr * sn + vt * cs);
   }
+}
+
+template <typename R>
+__device__ __forceinline__ void add_sources(const R (&w)[NV], const Metric<R>& m, int i, int j,
+                                            R omega, int gravity, int corot, R (&L)[NV]) {
+  add_sources_cm<R>(w, CellMetric<R>{m, i, j}, omega, gravity, corot, L);
 }
 
 }  // namespace icr

@@ -83,14 +83,15 @@ __device__ __forceinline__ void bnd_item(const RunDesc<R>* runs, const EnsTables
 
 template <typename R, int FLUX, int LIM, int STAGE>
 __device__ __forceinline__ void stage_item(const RunDesc<R>* runs, const EnsTables& e, int item,
-                                           int step, StageSmem<R, 64, 4>& sm) {
+                                           int step, StageW<R, 64, 4>& smw,
+                                           StageF<R, 64, 4>& smf) {
   const int r = find_run(e.tile_off, e.n_runs, item);
   const RunDesc<R>& rd = runs[r];
   const int local = item - e.tile_off[r];
   const int par = (rd.par + step) & 1;
   const int bx = local % rd.nbx, by = (local / rd.nbx) % rd.nby, bz = local / (rd.nbx * rd.nby);
   stage_tile<R, 64, 4, FLUX, LIM, STAGE>(STAGE == 1 ? rd.s1[par] : rd.s2[par], rd.planes, bx, by,
-                                         bz, local, sm);
+                                         bz, local, smw, smf);
 }
 
 template <typename R>
@@ -105,13 +106,14 @@ template <typename R, int FLUX, int LIM>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 k_ensemble(const RunDesc<R>* __restrict__ runs, EnsTables e, int nsteps) {
   const unsigned G = gridDim.x;
-  __shared__ StageSmem<R, 64, 4> sm;
+  __shared__ StageW<R, 64, 4> smw;
+  __shared__ StageF<R, 64, 4> smf;
   for (int s = 0; s < nsteps; ++s) {
     for_items(e.n_bitems, [&](int it) { bnd_item<R>(runs, e, it); });
     if (!grid_sync(e.bar, G, e.spin_limit)) return;
-    for_items(e.n_tiles, [&](int it) { stage_item<R, FLUX, LIM, 1>(runs, e, it, s, sm); });
+    for_items(e.n_tiles, [&](int it) { stage_item<R, FLUX, LIM, 1>(runs, e, it, s, smw, smf); });
     if (!grid_sync(e.bar, G, e.spin_limit)) return;
-    for_items(e.n_tiles, [&](int it) { stage_item<R, FLUX, LIM, 2>(runs, e, it, s, sm); });
+    for_items(e.n_tiles, [&](int it) { stage_item<R, FLUX, LIM, 2>(runs, e, it, s, smw, smf); });
     if (!grid_sync(e.bar, G, e.spin_limit)) return;
     for_items(e.n_runs, [&](int r) { fin_item<R>(runs, r); });
     if (!grid_sync(e.bar, G, e.spin_limit)) return;
@@ -126,8 +128,9 @@ __global__ void __launch_bounds__(256) k_ens_bnd(const RunDesc<R>* __restrict__ 
 template <typename R, int FLUX, int LIM, int STAGE>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 k_ens_stage(const RunDesc<R>* __restrict__ runs, EnsTables e, int step) {
-  __shared__ StageSmem<R, 64, 4> sm;
-  for_items(e.n_tiles, [&](int it) { stage_item<R, FLUX, LIM, STAGE>(runs, e, it, step, sm); });
+  __shared__ StageW<R, 64, 4> smw;
+  __shared__ StageF<R, 64, 4> smf;
+  for_items(e.n_tiles, [&](int it) { stage_item<R, FLUX, LIM, STAGE>(runs, e, it, step, smw, smf); });
 }
 template <typename R>
 __global__ void __launch_bounds__(256) k_ens_fin(const RunDesc<R>* __restrict__ runs, EnsTables e) {

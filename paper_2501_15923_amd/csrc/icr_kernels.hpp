@@ -180,13 +180,17 @@ __device__ __forceinline__ void write_partials(double* partials, int bid, double
 }
 
 // CFL rate of one cell from its primitives: sum_d (|v_d| + c_f,d) / dx_d.
+template <typename R, bool FAST = false, typename CM>
+__device__ __forceinline__ double cell_rate_cm(const R (&w)[NV], const CM& cm, R gam) {
+  const R lr = (fabs(w[1]) + cfast<R, 1, FAST>(w, gam)) * cm.r(MR_IDR);
+  const R lt = (fabs(w[2]) + cfast<R, 2, FAST>(w, gam)) * cm.r(MR_IRC) * cm.ilth();
+  const R lp = (fabs(w[3]) + cfast<R, 3, FAST>(w, gam)) * cm.r(MR_IRC) * cm.t(MT_ILPH);
+  return (double)(lr + lt + lp);
+}
 template <typename R, bool FAST = false>
 __device__ __forceinline__ double cell_rate(const R (&w)[NV], const Metric<R>& m, int i, int j,
                                             R gam) {
-  const R lr = (fabs(w[1]) + cfast<R, 1, FAST>(w, gam)) * ldg(m.idr, i);
-  const R lt = (fabs(w[2]) + cfast<R, 2, FAST>(w, gam)) * ldg(m.irc, i) * m.ilth;
-  const R lp = (fabs(w[3]) + cfast<R, 3, FAST>(w, gam)) * ldg(m.irc, i) * ldg(m.ilph, j);
-  return (double)(lr + lt + lp);
+  return cell_rate_cm<R, FAST>(w, CellMetric<R>{m, i, j}, gam);
 }
 
 template <typename R>

@@ -15,9 +15,10 @@ k_stage_lds(StageArgs<R> a, int kplanes) {
   const int nb = nbx * nby * gridDim.z;
   const int b = (blockIdx.z * nby + blockIdx.y) * nbx + blockIdx.x;
   const int tile = xcd_tile(b, nb);
-  __shared__ StageSmem<R, TR, TT> sm;
+  __shared__ StageW<R, TR, TT> smw;
+  __shared__ StageF<R, TR, TT> smf;
   stage_tile<R, TR, TT, FLUX, LIM, STAGE, FM>(a, kplanes, tile % nbx, (tile / nbx) % nby,
-                                              tile / (nbx * nby), tile, sm);
+                                              tile / (nbx * nby), tile, smw, smf);
 }
 
 template <typename R, int TR, int TT, int FLUX, int LIM, bool FM>

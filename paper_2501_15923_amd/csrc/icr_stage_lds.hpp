@@ -55,27 +55,77 @@ __device__ __forceinline__ void lds_face(const R* base, int stride, R gam, R igm
 // single-run kernel and by the ensemble kernels, so both execute the same
 // code.
 // LDS of one tile, indexed by lane along r (lane l holds cell i0 + l - 2):
-// primitives of rows -2 .. TT+1, the flux of r face i-1/2 at the lane of
-// cell i, the flux of theta face j-1/2 at row j (0 .. TT).  Declared once
-// per kernel and passed to stage_tile.
+// primitives of rows -2 .. TT+1 (StageW), the flux of r face i-1/2 at the
+// lane of cell i and the flux of theta face j-1/2 at row j (0 .. TT)
+// (StageF).  Two separate LDS objects, declared once per kernel and passed
+// to stage_tile: the compiler can then tell that the update's flux reads do
+// not touch the rows the stage-2 LDS-DMA copies are landing in, and does not
+// wait for those copies before them.
 template <typename R, int TR, int TT>
-struct StageSmem {
+struct alignas(16) StageW {
   R sW[NV][TT + 4][TR];
+};
+template <typename R, int TR, int TT>
+struct alignas(16) StageF {
   R sFr[NV][TT][TR];
   R sFt[NV][TT + 1][TR];
+  // the metric factors of the tile's cells, loaded once per block: per-r
+  // arrays at each lane's cell, per-theta arrays at each row's cell (the
+  // update then reads them from LDS instead of loading them every plane)
+  R mr[MR_N][TR];
+  R mt[MT_N][TT];
 };
 
-// FM: also store the stage's face mass fluxes (a.fmass, passive tracer on);
-// a compile-time switch so that the default kernel carries no trace of it.
+// Cell-metric accessor over the tile's LDS copy (lane li, row lj).
+template <typename R, int TR, int TT>
+struct LdsCellMetric {
+  const StageF<R, TR, TT>& f;
+  int li, lj;
+  R ilth_;
+  __device__ __forceinline__ R r(int a) const { return f.mr[a][li]; }
+  __device__ __forceinline__ R t(int a) const { return f.mt[a][lj]; }
+  __device__ __forceinline__ R ilth() const { return ilth_; }
+};
+
+// Stage-2 theta-halo copies: a halo region is the two rows on one side of
+// the tile (2 TR values of one variable, contiguous in LDS), copied by wave
+// instructions of 64 lanes x dw bytes (16 where a region is a multiple of
+// 1 KiB, else 4); instruction n of a plane covers chunk n % ipr of region
+// (n / ipr) % 2 of variable n / (2 ipr), and wave w issues n = w, w + nw,
+// ...  Each wave keeps the byte offsets of the first ppw of its (region,
+// chunk) pairs; this checks that they repeat with period ppw.
+// One LDS-DMA copy: every lane moves BYTES bytes from its own global
+// address to dst + BYTES * lane (dst is the same for the whole wave).
+template <int BYTES>
+__device__ __forceinline__ void lds_dma(const char* src, char* dst) {
+  static_assert(BYTES == 16 || BYTES == 4, "LDS-DMA copy width");
+  auto g = (const __attribute__((address_space(1))) void*)src;
+  auto l = (__attribute__((address_space(3))) void*)dst;
+  if constexpr (BYTES == 16)
+    __builtin_amdgcn_global_load_lds(g, l, 16, 0, 0);
+  else
+    __builtin_amdgcn_global_load_lds(g, l, 4, 0, 0);
+}
+
+constexpr bool dma_pairs_periodic(int nw, int ipr, int per_wave, int ppw) {
+  for (int w = 0; w < nw; ++w)
+    for (int m = 0; m < per_wave; ++m) {
+      const int n = w + nw * m, q = w + nw * (m % ppw);
+      if (n % ipr != q % ipr || (n / ipr) % 2 != (q / ipr) % 2) return false;
+    }
+  return true;
+}
+
 template <typename R, int TR, int TT, int FLUX, int LIM, int STAGE, bool FM = false>
 __device__ __forceinline__ void stage_tile(const StageArgs<R>& a, int kplanes, int bx, int by,
-                                           int bz, int pslot, StageSmem<R, TR, TT>& sm) {
+                                           int bz, int pslot, StageW<R, TR, TT>& smw,
+                                           StageF<R, TR, TT>& smf) {
   constexpr int NT = TR * TT;
   constexpr int TI = tile_cells_r(TR);
   constexpr int WT = TT + 4;
-  auto& sW = sm.sW;
-  auto& sFr = sm.sFr;
-  auto& sFt = sm.sFt;
+  auto& sW = smw.sW;
+  auto& sFr = smf.sFr;
+  auto& sFt = smf.sFt;
 
   const int ti = threadIdx.x, tj = threadIdx.y, tid = tj * TR + ti;
   const int i0 = bx * TI, j0 = by * TT, k0 = bz * kplanes;
@@ -121,6 +171,29 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R>& a, int kplanes, i
     return;
   }
 
+  // metric factors of the tile into LDS (visible after the first plane
+  // barrier; the first use is after it).  A block that runs several tiles
+  // (ensembles) first waits until every wave has left the previous tile.
+  __syncthreads();
+  // (array indices are compile-time constants after unrolling, so that the
+  // metric pointers stay kernel arguments)
+  for (int l = tid; l < TR; l += NT) {
+    const int ii = i0 + l - 2;
+    const int icl = ii < 0 ? (a.asymm ? (-1 - ii < nr ? -1 - ii : nr - 1) : 0)
+                           : (ii < nr ? ii : nr - 1);
+#pragma unroll
+    for (int arr = 0; arr < MR_N; ++arr) smf.mr[arr][l] = ldg(metric_r(a.m, arr), (unsigned)icl);
+  }
+  for (int row = tid; row < TT; row += NT) {
+    const int jr = j0 + row < nt ? j0 + row : nt - 1;
+#pragma unroll
+    for (int arr = 0; arr < MT_N; ++arr) smf.mt[arr][row] = ldg(metric_t(a.m, arr), (unsigned)jr);
+  }
+  const LdsCellMetric<R, TR, TT> cm{smf, ti, tj, a.m.ilth};
+  // the stage's dt, read once: a global load inside the update would make
+  // it wait for the stage-2 halo copies issued before it
+  const R dt = (R)a.clock->dt;
+
   // phi ring of the own column: at the top of iteration k, wa = W(k-1),
   // wb = W(k), wc = W(k+1) and fcar = flux of face k-1/2.  Iteration k0-1
   // only forms fcar, through the same code as every later phi face.
@@ -132,10 +205,17 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R>& a, int kplanes, i
   for (int v = 0; v < NV; ++v) fcar[v] = R(0);
 
   // Stage 1 (PF): this thread's theta-halo item is the same (row, lane) of
-  // every plane, and the next plane's item is loaded while the current
-  // plane is processed.  Stage 2 has no registers to spare for it and
-  // loads each plane's halo after the plane barrier.
+  // every plane, and the next plane's item is loaded into registers while
+  // the current plane is processed.  Stage 2 (DMA) has no registers to
+  // spare: the next plane's halo rows are copied global -> LDS by the LDS-DMA
+  // loads, issued after the plane's face barrier (nothing reads sW until the
+  // next plane barrier), so they travel while the plane is updated; after
+  // the next plane barrier each thread converts its halo cell to primitives
+  // in place.  Those copies take, for a halo cell below r_in or beyond
+  // r_out, the clamped cell of its row: such cells only feed the theta
+  // faces of halo lanes, which the update never reads.
   constexpr bool PF = STAGE == 1;
+  constexpr bool DMA = STAGE == 2;
   static_assert(4 * TR <= NT, "at most one theta-halo item per thread");
   const bool hv = tid < 4 * TR;
   const int hrow = tid / TR, hl = tid - hrow * TR;
@@ -169,6 +249,55 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R>& a, int kplanes, i
   R hraw[NV];
   if (PF && hv && k0 < kend) halo_raw(k0, hraw);
 
+  // (the copies need n_r >= 2: a 16-byte copy takes two neighbouring cells
+  // of a row; with fewer cells stage 2 loads its halo after the barrier)
+  constexpr int NW = NT / 64;                              // waves per block
+  constexpr int RB = 2 * TR * (int)sizeof(R);              // bytes of a halo region
+  constexpr int DW = RB % 1024 == 0 ? 16 : 4;              // bytes per lane and copy
+  constexpr int IPR = RB / (64 * DW) > 0 ? RB / (64 * DW) : 1;  // copies per region
+  constexpr int NINS = NV * 2 * IPR;                       // per plane
+  constexpr int PPW = 2 * IPR > NW ? 2 * IPR / NW : 1;     // (region, chunk) pairs per wave
+  constexpr int SPAN = DW / (int)sizeof(R) > 1 ? DW / (int)sizeof(R) : 1;  // cells per copy
+  static_assert(!DMA || (NT % 64 == 0 && RB % (64 * DW) == 0 && NINS % NW == 0 &&
+                         dma_pairs_periodic(NW, IPR, NINS / NW, PPW) && SPAN <= 2 &&
+                         tile_cells_r(TR) % 2 == 0),
+                "theta-halo DMA layout");
+  const bool dma_on = DMA && nr >= 2;  // uniform
+  const int wv = __builtin_amdgcn_readfirstlane(tid) >> 6;  // wave index (uniform)
+  unsigned doff[PPW];  // byte offset in a plane of this lane's dw bytes, per pair
+  if constexpr (DMA) {
+    const int lane = tid & 63;
+#pragma unroll
+    for (int p = 0; p < PPW; ++p) {
+      const int n = wv + NW * p;
+      const int c = n % IPR, reg = (n / IPR) % 2;
+      const int b = (c * 64 + lane) * DW;
+      const int e = b / (int)sizeof(R);  // first value of this lane's copy
+      const int rr = e / TR, l = e - rr * TR;
+      bool fl;
+      const int gj = mirror_row(j0 + (reg ? TT + rr : rr - 2), nt, fl);
+      // clamped into the row; a two-cell copy keeps both cells in the row
+      int gi = i0 + l - 2;
+      gi = gi < 0 ? 0 : (gi <= nr - SPAN ? gi : nr - SPAN);
+      doff[p] = (unsigned)(gj * nr + gi) * (unsigned)sizeof(R) + (unsigned)(b % (int)sizeof(R));
+    }
+  }
+  auto dma_halo = [&](int k) {
+    const unsigned kb = (unsigned)k * plane_cells * (unsigned)sizeof(R);
+#pragma unroll
+    for (int m = 0; m < NINS / NW; ++m) {
+      const int n = wv + NW * m;
+      const int c = n % IPR, reg = (n / IPR) % 2, v = n / (2 * IPR);
+      const char* src = reinterpret_cast<const char*>(a.uin + (size_t)v * a.ncell) + kb +
+                        doff[m % PPW];
+      char* dst = reinterpret_cast<char*>(&sW[v][reg ? TT + 2 : 0][0]) + c * 64 * DW;
+      lds_dma<DW>(src, dst);
+    }
+  };
+  if constexpr (DMA) {
+    if (dma_on && k0 < kend) dma_halo(k0);
+  }
+
   double lam = 0.0, s1 = 0.0, s0 = 0.0;
   int bad = BAD_NONE;
 
@@ -176,6 +305,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R>& a, int kplanes, i
     const bool body = k >= k0;  // uniform over the block
     const unsigned kbase = (unsigned)k * plane_cells;
     if (body) {
+      // stage 2: this wave's halo copies have landed (s_waitcnt vmcnt(0));
+      // the barrier then makes every wave's copies visible
+      if constexpr (DMA) {
+        if (dma_on) __builtin_amdgcn_s_waitcnt(0x3f70);
+      }
       __syncthreads();  // the previous plane's LDS reads are complete
       if (lghost) {  // inner ghost (primitives) at this lane's row
         R w[NV];
@@ -199,6 +333,26 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R>& a, int kplanes, i
         if (hv) {
           halo_put(hraw);
           if (k + 1 < kend) halo_raw(k + 1, hraw);  // in flight during this plane
+        }
+      } else if (dma_on) {
+        if (hv) {  // conserved -> primitive in place
+          R u[NV], w[NV];
+          // a two-cell copy starts at an even lane (an even cell, the tile
+          // start being even): at the end of a row of odd length it was
+          // shifted back into the row, so the even lane of the last cell got
+          // its left neighbour; reload that one cell
+          if (SPAN == 2 && hgi == nr - 1 && (hl & 1) == 0 && hl >= 2 && hl < TR - 2) {
+#pragma unroll
+            for (int v = 0; v < NV; ++v)
+              u[v] = ldg(a.uin + v * a.ncell, kbase + (unsigned)(hgj * nr + hgi));
+          } else {
+#pragma unroll
+            for (int v = 0; v < NV; ++v) u[v] = sW[v][hjj + 2][hl];
+          }
+          cons2prim<R, true>(u, w, a.gm1);
+          if (hflip) flip_theta(w);
+#pragma unroll
+          for (int v = 0; v < NV; ++v) sW[v][hjj + 2][hl] = w[v];
         }
       } else {
         for (int h = tid; h < 4 * TR; h += NT) {
@@ -274,11 +428,14 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R>& a, int kplanes, i
     // now wa = W(k), wb = W(k+1), wc = W(k+2)
     if (body) {
       __syncthreads();  // r / theta face fluxes are in LDS
+      if constexpr (DMA) {
+        if (dma_on && k + 1 < kend) dma_halo(k + 1);  // in flight during this update
+      }
       if (valid) {
-        const R rm2 = ldg(a.m.rm2, ic), rp2 = ldg(a.m.rp2, ic), ivr = ldg(a.m.ivr, ic);
-        const R hr = ldg(a.m.hr, ic);
-        const R sm = ldg(a.m.sm, jc), sp = ldg(a.m.sp, jc), ict = ldg(a.m.ict, jc);
-        const R fph = hr * ldg(a.m.phf, jc);
+        const R rm2 = cm.r(MR_RM2), rp2 = cm.r(MR_RP2), ivr = cm.r(MR_IVR);
+        const R hr = cm.r(MR_HR);
+        const R sm = cm.t(MT_SM), sp = cm.t(MT_SP), ict = cm.t(MT_ICT);
+        const R fph = hr * cm.t(MT_PHF);
         R L[NV];
 #pragma unroll
         for (int v = 0; v < NV; ++v) {
@@ -287,12 +444,11 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R>& a, int kplanes, i
           L[v] -= hr * (sp * sFt[v][tj + 1][ti] - sm * sFt[v][tj][ti]) * ict;
           L[v] -= fph * (fhi[v] - fcar[v]);
         }
-        add_sources<R>(wa, a.m, ic, jc, a.omega, a.gravity, a.corot, L);
+        add_sources_cm<R>(wa, cm, a.omega, a.gravity, a.corot, L);
         // the stage's own conserved state, rebuilt from the ring's primitives
         // (equal to the stored values up to rounding; no reload)
         R uc[NV];
         prim2cons<R>(wa, uc, a.igm1);
-        const R dt = (R)a.clock->dt;
         const unsigned c = kbase + colbase;
         if constexpr (FM) {  // passive tracer on: keep this stage's mass fluxes
           stg(a.fmass, c, sFr[0][tj][ti]);
@@ -313,7 +469,7 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R>& a, int kplanes, i
             stg(a.uout + v * a.ncell, c, unew[v]);
           }
           cons2prim<R, true>(unew, wn, a.gm1);
-          lam = fmax(lam, cell_rate<R, true>(wn, a.m, ic, jc, a.gam));
+          lam = fmax(lam, cell_rate_cm<R, true>(wn, cm, a.gam));
           const double d = (double)unew[0] - (double)un[0];
           s1 += d * d;
           s0 += (double)un[0] * (double)un[0];

@@ -141,7 +141,8 @@ def test_options_parity(mods):
         parity.assert_parity(*cons(mods, s, o), what=f"gravity={grav} corot={corot}")
 
 
-@pytest.mark.parametrize("shape", [(3, 1, 1), (5, 1, 7), (9, 3, 1), (70, 2, 3)])
+@pytest.mark.parametrize("shape", [(3, 1, 1), (5, 1, 7), (9, 3, 1), (70, 2, 3), (1, 4, 6),
+                                   (61, 5, 8), (123, 7, 5)])
 def test_degenerate_grids_parity(mods, shape):
     g = synth.Grid(*shape)
     m = synth.static_map(g, 1)
