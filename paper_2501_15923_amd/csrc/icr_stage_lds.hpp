@@ -156,6 +156,17 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R>& a, int kplanes, i
   // The ring of the first tile's two halo lanes below r_in holds cell 0 (or
   // the mirror cell); those lanes put the inner ghost into LDS instead (see
   // below).
+  // the next plane's own-column state is loaded one plane ahead (raw
+  // conserved values in uring) and converted when the phi face needs it
+  auto own_raw = [&](int k, R (&u)[NV]) {
+    const unsigned c = (unsigned)wrap_phi(k, np) * plane_cells + lbase;
+#pragma unroll
+    for (int v = 0; v < NV; ++v) u[v] = ldg(a.uin + v * a.ncell, c);
+  };
+  auto own_cvt = [&](const R (&u)[NV], R (&w)[NV]) {
+    cons2prim<R, true>(u, w, a.gm1);
+    if (flipj) flip_theta(w);
+  };
   auto load_own = [&](int k, R (&w)[NV]) {
     load_cons_prim<R, true>(a, (unsigned)wrap_phi(k, np) * plane_cells + lbase, w);
     if (flipj) flip_theta(w);
@@ -201,6 +212,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R>& a, int kplanes, i
   load_own(k0 - 2, wa);
   load_own(k0 - 1, wb);
   load_own(k0, wc);
+  R uring[NV];
+  own_raw(k0 + 1, uring);
 #pragma unroll
   for (int v = 0; v < NV; ++v) fcar[v] = R(0);
 
@@ -415,7 +428,8 @@ __device__ __forceinline__ void stage_tile(const StageArgs<R>& a, int kplanes, i
     R fhi[NV];
     {
       R wd[NV], wl[NV], wr[NV];
-      load_own(k + 2, wd);
+      own_cvt(uring, wd);      // W(k + 2), loaded one plane ago
+      own_raw(k + 3, uring);   // in flight until the next plane's phi face
       reconstruct<R, LIM, true>(wa, wb, wc, wd, wl, wr);
       face_flux<R, 3, FLUX, true>(wl, wr, a.gam, a.igm1, fhi);
 #pragma unroll
