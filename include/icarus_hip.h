@@ -116,8 +116,7 @@ typedef struct {
   int precision;             /* ICR_PREC_F64 or ICR_PREC_F32             */
   int gravity;               /* 1: include -GM/r^2 e_r                   */
   int corotation;            /* 1: centrifugal + Coriolis sources        */
-  int tracer;                /* 1: carry the passive CME tracer (single
-                                solvers only; ensembles reject it)       */
+  int tracer;                /* 1: carry the passive CME tracer          */
   int bc_transverse;         /* ICR_BCT_MAP or ICR_BCT_ASYMM             */
 } icr_phys;
 
@@ -335,7 +334,8 @@ int icr_fast_math(const double *x, long long n, double *rcp, double *sq, void *h
  * Batched ensemble (not in the paper; many independent runs on one GPU).
  * n_runs solvers with their own grids, boundary maps, cone CMEs, clocks and
  * CFL dt, stepped together: each ensemble step walks all runs' boundary
- * columns, stage-1 tiles, stage-2 tiles and per-run finalize.  In the
+ * columns, stage-1 tiles, stage-2 tiles and per-run finalize (with the
+ * passive tracer, a tracer list of all runs' cells follows each stage).  In the
  * persistent mode one kernel launch performs the steps with a device-wide
  * barrier between those phases (its grid never exceeds the resident block
  * capacity; a barrier that cannot complete turns into ICR_ERR_HIP instead of
@@ -345,7 +345,9 @@ int icr_fast_math(const double *x, long long n, double *rcp, double *sq, void *h
  * ------------------------------------------------------------------------ */
 typedef struct icr_ensemble icr_ensemble;
 
-/* Device bytes for n_runs grids (grids[n_runs]) sharing one icr_phys. */
+/* Device bytes for n_runs grids (grids[n_runs]) sharing one icr_phys.
+ * Every flux and the tracer are supported; WENO5 is not
+ * (ICR_ERR_UNSUPPORTED). */
 int icr_ens_workspace_bytes(int n_runs, const icr_grid *grids,
                             const icr_phys *phys, size_t *bytes);
 

@@ -1205,10 +1205,11 @@ struct icr_ensemble {
   void* d_runs;
   int* d_tile_off;
   int* d_bnd_off;
+  int* d_trc_off;
   GridBar* d_bar;
   DevClock** d_clocks;
   DevClock* d_gather;
-  int n_tiles, n_bitems;
+  int n_tiles, n_bitems, n_titems;
   int persistent, grid, use_graphs;
   long long spin_limit;
   hipGraphExec_t g_chunk;
@@ -1221,7 +1222,7 @@ namespace {
 size_t ens_table_bytes(int n) {
   size_t b = 0;
   b += align_up(sizeof(RunDesc<double>) * n);
-  b += 2 * align_up(sizeof(int) * (n + 1));
+  b += 3 * align_up(sizeof(int) * (n + 1));
   b += align_up(sizeof(GridBar));
   b += align_up(sizeof(DevClock*) * n);
   b += align_up(sizeof(DevClock) * n);
@@ -1235,9 +1236,20 @@ RunDesc<R> make_desc(icr_solver* s, int planes) {
     d.s1[p] = s->stage_args<R>(p, p, 2, 0);
     d.s2[p] = s->stage_args<R>(2, p, p ^ 1, 1);
   }
+  for (int p = 0; p < 2; ++p) {
+    if (s->trc()) {
+      d.t1[p] = s->tracer_args<R>(p, p, p, 2, 0);
+      d.t2[p] = s->tracer_args<R>(2, 2, p, p ^ 1, 1);
+    } else {
+      std::memset(&d.t1[p], 0, sizeof d.t1[p]);
+      std::memset(&d.t2[p], 0, sizeof d.t2[p]);
+    }
+  }
   d.bnd = s->bnd();
   d.ghost0 = (R*)s->ghost(0);
   d.ghost1 = (R*)s->ghost(1);
+  d.tghost0 = (R*)s->tg(0);
+  d.tghost1 = (R*)s->tg(1);
   d.clock = s->clock();
   d.partials = (double*)(s->ws + s->L.partials);
   d.nbx = (s->g.n_r + tile_cells_r(64) - 1) / tile_cells_r(64);
@@ -1251,7 +1263,7 @@ RunDesc<R> make_desc(icr_solver* s, int planes) {
 
 int ens_upload(icr_ensemble* e) {
   const int n = e->n;
-  std::vector<int> toff(n + 1, 0), boff(n + 1, 0);
+  std::vector<int> toff(n + 1, 0), boff(n + 1, 0), coff(n + 1, 0);
   std::vector<char> host(sizeof(RunDesc<double>) * n);
   for (int r = 0; r < n; ++r) {
     icr_solver* s = e->runs[r];
@@ -1265,14 +1277,18 @@ int ens_upload(icr_ensemble* e) {
       toff[r + 1] = toff[r] + d.nbx * d.nby * d.nbz;
     }
     boff[r + 1] = boff[r] + (s->g.n_theta * s->g.n_phi + 255) / 256;
+    coff[r + 1] = coff[r] + (s->trc() ? (int)((s->ncell() + 255) / 256) : 0);
   }
   e->n_tiles = toff[n];
   e->n_bitems = boff[n];
+  e->n_titems = coff[n];
   const size_t rb = e->f32 ? sizeof(RunDesc<float>) * n : sizeof(RunDesc<double>) * n;
   HIP_TRY(hipMemcpyAsync(e->d_runs, host.data(), rb, hipMemcpyHostToDevice, e->stream));
   HIP_TRY(hipMemcpyAsync(e->d_tile_off, toff.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice,
                          e->stream));
   HIP_TRY(hipMemcpyAsync(e->d_bnd_off, boff.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice,
+                         e->stream));
+  HIP_TRY(hipMemcpyAsync(e->d_trc_off, coff.data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice,
                          e->stream));
   HIP_TRY(hipStreamSynchronize(e->stream));
   return ICR_OK;
@@ -1284,6 +1300,8 @@ EnsLaunch ens_launch_args(icr_ensemble* e, int nsteps) {
   L.e.n_runs = e->n;
   L.e.n_tiles = e->n_tiles;
   L.e.n_bitems = e->n_bitems;
+  L.e.n_titems = e->n_titems;
+  L.e.trc_off = e->d_trc_off;
   L.e.tile_off = e->d_tile_off;
   L.e.bnd_off = e->d_bnd_off;
   L.e.bar = e->d_bar;
@@ -1293,6 +1311,7 @@ EnsLaunch ens_launch_args(icr_ensemble* e, int nsteps) {
   L.nsteps = nsteps;
   L.flux = e->p.flux;
   L.lim = e->p.limiter;
+  L.tracer = e->p.tracer ? 1 : 0;
   return L;
 }
 
@@ -1307,10 +1326,6 @@ extern "C" {
 
 int icr_ens_workspace_bytes(int n, const icr_grid* grids, const icr_phys* phys, size_t* bytes) {
   if (n < 1 || !grids || !bytes) return fail(ICR_ERR_ARG, "need n >= 1, grids and bytes");
-  if (phys && phys->tracer)
-    return fail(ICR_ERR_UNSUPPORTED, "the passive tracer is available for single solvers only");
-  if (phys && phys->flux == ICR_FLUX_HLLD)
-    return fail(ICR_ERR_UNSUPPORTED, "the HLLD flux is available for single solvers only");
   if (phys && phys->limiter == ICR_LIM_WENO5)
     return fail(ICR_ERR_UNSUPPORTED, "WENO5 is available for single solvers only");
   size_t total = ens_table_bytes(n);
@@ -1345,6 +1360,8 @@ int icr_ens_create(int n, const icr_grid* grids, const icr_phys* phys, void* ws,
   e->d_tile_off = (int*)t;
   t += align_up(sizeof(int) * (n + 1));
   e->d_bnd_off = (int*)t;
+  t += align_up(sizeof(int) * (n + 1));
+  e->d_trc_off = (int*)t;
   t += align_up(sizeof(int) * (n + 1));
   e->d_bar = (GridBar*)t;
   t += align_up(sizeof(GridBar));
@@ -1386,7 +1403,7 @@ int icr_ens_create(int n, const icr_grid* grids, const icr_phys* phys, void* ws,
   int dev = 0, cus = 0;
   HIP_TRY(hipGetDevice(&dev));
   HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-  const int per_cu = ensemble_blocks_per_cu(e->f32, phys->flux, phys->limiter);
+  const int per_cu = ensemble_blocks_per_cu(e->f32, phys->flux, phys->limiter, phys->tracer != 0);
   e->grid = (per_cu > 0 ? per_cu : 1) * cus;
   e->grid -= e->grid % NXCD;
   if (e->grid < NXCD) e->grid = NXCD;
@@ -1427,7 +1444,7 @@ int icr_ens_set_mode(icr_ensemble* e, int persistent, int grid_blocks, int use_g
     int dev = 0, cus = 0;
     HIP_TRY(hipGetDevice(&dev));
     HIP_TRY(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
-    const int per_cu = ensemble_blocks_per_cu(e->f32, e->p.flux, e->p.limiter);
+    const int per_cu = ensemble_blocks_per_cu(e->f32, e->p.flux, e->p.limiter, e->p.tracer != 0);
     if (grid_blocks % NXCD != 0 || grid_blocks > per_cu * cus)
       return fail(ICR_ERR_ARG, "grid_blocks must be a multiple of 8 and <= %d resident blocks",
                   per_cu * cus);

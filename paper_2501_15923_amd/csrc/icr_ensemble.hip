@@ -75,13 +75,30 @@ __device__ __forceinline__ void bnd_item(const RunDesc<R>* runs, const EnsTables
   if (q >= plane || !rd.clock->active) return;
   const int j = q % rd.bnd.nt, k = q / rd.bnd.nt;
   double w[NV];
-  boundary_prim(rd.bnd, rd.clock->t, j, k, w);
+  int in0, in1;
+  boundary_prim(rd.bnd, rd.clock->t, j, k, w, &in0);
   for (int v = 0; v < NV; ++v) rd.ghost0[(long long)v * plane + q] = (R)w[v];
-  boundary_prim(rd.bnd, rd.clock->t + rd.clock->dt, j, k, w);
+  boundary_prim(rd.bnd, rd.clock->t + rd.clock->dt, j, k, w, &in1);
   for (int v = 0; v < NV; ++v) rd.ghost1[(long long)v * plane + q] = (R)w[v];
+  if (rd.tghost0) {  // tracer of the inner ghost cells: inside an inserted cone
+    rd.tghost0[q] = (R)in0;
+    rd.tghost1[q] = (R)in1;
+  }
 }
 
-template <typename R, int FLUX, int LIM, int STAGE>
+// Tracer item: 256 cells of one run, after that run's stage tiles.
+template <typename R, int STAGE>
+__device__ __forceinline__ void trc_item(const RunDesc<R>* runs, const EnsTables& e, int item,
+                                         int step) {
+  const int r = find_run(e.trc_off, e.n_runs, item);
+  const RunDesc<R>& rd = runs[r];
+  const int par = (rd.par + step) & 1;
+  const int tid = threadIdx.y * blockDim.x + threadIdx.x;
+  const long long c = (long long)(item - e.trc_off[r]) * 256 + tid;
+  tracer_cell<R, STAGE>(STAGE == 1 ? rd.t1[par] : rd.t2[par], c);
+}
+
+template <typename R, int FLUX, int LIM, int STAGE, bool FM>
 __device__ __forceinline__ void stage_item(const RunDesc<R>* runs, const EnsTables& e, int item,
                                            int step, StageW<R, 64, 4>& smw,
                                            StageF<R, 64, 4>& smf) {
@@ -90,8 +107,8 @@ __device__ __forceinline__ void stage_item(const RunDesc<R>* runs, const EnsTabl
   const int local = item - e.tile_off[r];
   const int par = (rd.par + step) & 1;
   const int bx = local % rd.nbx, by = (local / rd.nbx) % rd.nby, bz = local / (rd.nbx * rd.nby);
-  stage_tile<R, 64, 4, FLUX, LIM, STAGE>(STAGE == 1 ? rd.s1[par] : rd.s2[par], rd.planes, bx, by,
-                                         bz, local, smw, smf);
+  stage_tile<R, 64, 4, FLUX, LIM, STAGE, FM>(STAGE == 1 ? rd.s1[par] : rd.s2[par], rd.planes, bx,
+                                             by, bz, local, smw, smf);
 }
 
 template <typename R>
@@ -102,7 +119,9 @@ __device__ __forceinline__ void fin_item(const RunDesc<R>* runs, int r) {
                   (const R*)nullptr, nullptr);
 }
 
-template <typename R, int FLUX, int LIM>
+// FM: the passive tracer is on (stage tiles keep their face mass fluxes, a
+// tracer list follows each stage list).
+template <typename R, int FLUX, int LIM, bool FM>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 k_ensemble(const RunDesc<R>* __restrict__ runs, EnsTables e, int nsteps) {
   const unsigned G = gridDim.x;
@@ -111,10 +130,18 @@ k_ensemble(const RunDesc<R>* __restrict__ runs, EnsTables e, int nsteps) {
   for (int s = 0; s < nsteps; ++s) {
     for_items(e.n_bitems, [&](int it) { bnd_item<R>(runs, e, it); });
     if (!grid_sync(e.bar, G, e.spin_limit)) return;
-    for_items(e.n_tiles, [&](int it) { stage_item<R, FLUX, LIM, 1>(runs, e, it, s, smw, smf); });
+    for_items(e.n_tiles, [&](int it) { stage_item<R, FLUX, LIM, 1, FM>(runs, e, it, s, smw, smf); });
     if (!grid_sync(e.bar, G, e.spin_limit)) return;
-    for_items(e.n_tiles, [&](int it) { stage_item<R, FLUX, LIM, 2>(runs, e, it, s, smw, smf); });
+    if constexpr (FM) {
+      for_items(e.n_titems, [&](int it) { trc_item<R, 1>(runs, e, it, s); });
+      if (!grid_sync(e.bar, G, e.spin_limit)) return;
+    }
+    for_items(e.n_tiles, [&](int it) { stage_item<R, FLUX, LIM, 2, FM>(runs, e, it, s, smw, smf); });
     if (!grid_sync(e.bar, G, e.spin_limit)) return;
+    if constexpr (FM) {
+      for_items(e.n_titems, [&](int it) { trc_item<R, 2>(runs, e, it, s); });
+      if (!grid_sync(e.bar, G, e.spin_limit)) return;
+    }
     for_items(e.n_runs, [&](int r) { fin_item<R>(runs, r); });
     if (!grid_sync(e.bar, G, e.spin_limit)) return;
   }
@@ -125,12 +152,18 @@ template <typename R>
 __global__ void __launch_bounds__(256) k_ens_bnd(const RunDesc<R>* __restrict__ runs, EnsTables e) {
   for_items(e.n_bitems, [&](int it) { bnd_item<R>(runs, e, it); });
 }
-template <typename R, int FLUX, int LIM, int STAGE>
+template <typename R, int FLUX, int LIM, int STAGE, bool FM>
 __global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
 k_ens_stage(const RunDesc<R>* __restrict__ runs, EnsTables e, int step) {
   __shared__ StageW<R, 64, 4> smw;
   __shared__ StageF<R, 64, 4> smf;
-  for_items(e.n_tiles, [&](int it) { stage_item<R, FLUX, LIM, STAGE>(runs, e, it, step, smw, smf); });
+  for_items(e.n_tiles,
+            [&](int it) { stage_item<R, FLUX, LIM, STAGE, FM>(runs, e, it, step, smw, smf); });
+}
+template <typename R, int STAGE>
+__global__ void __launch_bounds__(256) k_ens_trc(const RunDesc<R>* __restrict__ runs, EnsTables e,
+                                                 int step) {
+  for_items(e.n_titems, [&](int it) { trc_item<R, STAGE>(runs, e, it, step); });
 }
 template <typename R>
 __global__ void __launch_bounds__(256) k_ens_fin(const RunDesc<R>* __restrict__ runs, EnsTables e) {
@@ -153,32 +186,45 @@ __global__ void k_ens_gather(DevClock* const* __restrict__ clocks, int n, DevClo
   if (r < n) out[r] = *clocks[r];
 }
 
-template <typename R, int FLUX, int LIM>
+template <typename R, int FLUX, int LIM, bool FM>
 static void ens_launch(const EnsLaunch& L, hipStream_t s) {
   const RunDesc<R>* runs = (const RunDesc<R>*)L.runs;
   const dim3 blk(64, 4);
   if (L.persistent) {
-    hipLaunchKernelGGL((k_ensemble<R, FLUX, LIM>), dim3(L.grid), blk, 0, s, runs, L.e, L.nsteps);
+    hipLaunchKernelGGL((k_ensemble<R, FLUX, LIM, FM>), dim3(L.grid), blk, 0, s, runs, L.e,
+                       L.nsteps);
     return;
   }
   auto items = [](int n) { return dim3((unsigned)((n + NXCD - 1) / NXCD * NXCD)); };
   for (int q = 0; q < L.nsteps; ++q) {
     hipLaunchKernelGGL(k_ens_bnd<R>, items(L.e.n_bitems), blk, 0, s, runs, L.e);
-    hipLaunchKernelGGL((k_ens_stage<R, FLUX, LIM, 1>), items(L.e.n_tiles), blk, 0, s, runs, L.e, q);
-    hipLaunchKernelGGL((k_ens_stage<R, FLUX, LIM, 2>), items(L.e.n_tiles), blk, 0, s, runs, L.e, q);
+    hipLaunchKernelGGL((k_ens_stage<R, FLUX, LIM, 1, FM>), items(L.e.n_tiles), blk, 0, s, runs,
+                       L.e, q);
+    if (FM) hipLaunchKernelGGL((k_ens_trc<R, 1>), items(L.e.n_titems), blk, 0, s, runs, L.e, q);
+    hipLaunchKernelGGL((k_ens_stage<R, FLUX, LIM, 2, FM>), items(L.e.n_tiles), blk, 0, s, runs,
+                       L.e, q);
+    if (FM) hipLaunchKernelGGL((k_ens_trc<R, 2>), items(L.e.n_titems), blk, 0, s, runs, L.e, q);
     hipLaunchKernelGGL(k_ens_fin<R>, items(L.e.n_runs), blk, 0, s, runs, L.e);
   }
 }
 
+template <typename R, int FLUX, int LIM>
+static void ens_launch_fm(const EnsLaunch& L, hipStream_t s) {
+  if (L.tracer) ens_launch<R, FLUX, LIM, true>(L, s);
+  else ens_launch<R, FLUX, LIM, false>(L, s);
+}
+
+template <typename R, int FLUX>
+static void ens_launch_lim(const EnsLaunch& L, hipStream_t s) {
+  if (L.lim == LIM_MINMOD) ens_launch_fm<R, FLUX, LIM_MINMOD>(L, s);
+  else ens_launch_fm<R, FLUX, LIM_MC>(L, s);
+}
+
 template <typename R>
 static void ens_dispatch(const EnsLaunch& L, hipStream_t s) {
-  if (L.flux == FLUX_TVDLF) {
-    if (L.lim == LIM_MINMOD) ens_launch<R, FLUX_TVDLF, LIM_MINMOD>(L, s);
-    else ens_launch<R, FLUX_TVDLF, LIM_MC>(L, s);
-  } else {
-    if (L.lim == LIM_MINMOD) ens_launch<R, FLUX_HLL, LIM_MINMOD>(L, s);
-    else ens_launch<R, FLUX_HLL, LIM_MC>(L, s);
-  }
+  if (L.flux == FLUX_TVDLF) ens_launch_lim<R, FLUX_TVDLF>(L, s);
+  else if (L.flux == FLUX_HLLD) ens_launch_lim<R, FLUX_HLLD>(L, s);
+  else ens_launch_lim<R, FLUX_HLL>(L, s);
 }
 
 void launch_ensemble(const EnsLaunch& L, bool f32, hipStream_t s) {
@@ -194,18 +240,25 @@ void launch_ens_gather(DevClock* const* clocks, int n, DevClock* out, hipStream_
   hipLaunchKernelGGL(k_ens_gather, dim3((n + 63) / 64), dim3(64), 0, s, clocks, n, out);
 }
 
-int ensemble_blocks_per_cu(bool f32, int flux, int lim) {
+template <typename R, int FLUX, int LIM>
+static const void* ens_fn(bool tracer) {
+  return tracer ? reinterpret_cast<const void*>(&k_ensemble<R, FLUX, LIM, true>)
+                : reinterpret_cast<const void*>(&k_ensemble<R, FLUX, LIM, false>);
+}
+
+template <typename R>
+static const void* ens_fn_r(int flux, int lim, bool tracer) {
+  const bool mm = lim == LIM_MINMOD;
+  if (flux == FLUX_TVDLF)
+    return mm ? ens_fn<R, FLUX_TVDLF, LIM_MINMOD>(tracer) : ens_fn<R, FLUX_TVDLF, LIM_MC>(tracer);
+  if (flux == FLUX_HLLD)
+    return mm ? ens_fn<R, FLUX_HLLD, LIM_MINMOD>(tracer) : ens_fn<R, FLUX_HLLD, LIM_MC>(tracer);
+  return mm ? ens_fn<R, FLUX_HLL, LIM_MINMOD>(tracer) : ens_fn<R, FLUX_HLL, LIM_MC>(tracer);
+}
+
+int ensemble_blocks_per_cu(bool f32, int flux, int lim, bool tracer) {
   int nb = 0;
-  const void* fn = nullptr;
-#define ICR_ENS_FN(R, F, L) reinterpret_cast<const void*>(&k_ensemble<R, F, L>)
-  if (f32)
-    fn = flux == FLUX_TVDLF ? (lim == LIM_MINMOD ? ICR_ENS_FN(float, 0, 0) : ICR_ENS_FN(float, 0, 1))
-                            : (lim == LIM_MINMOD ? ICR_ENS_FN(float, 1, 0) : ICR_ENS_FN(float, 1, 1));
-  else
-    fn = flux == FLUX_TVDLF
-             ? (lim == LIM_MINMOD ? ICR_ENS_FN(double, 0, 0) : ICR_ENS_FN(double, 0, 1))
-             : (lim == LIM_MINMOD ? ICR_ENS_FN(double, 1, 0) : ICR_ENS_FN(double, 1, 1));
-#undef ICR_ENS_FN
+  const void* fn = f32 ? ens_fn_r<float>(flux, lim, tracer) : ens_fn_r<double>(flux, lim, tracer);
   if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, fn, 256, 0) != hipSuccess) return 0;
   return nb;
 }

@@ -17,9 +17,12 @@ struct GridBar {
 template <typename R>
 struct RunDesc {
   StageArgs<R> s1[2], s2[2];
+  TracerArgs<R> t1[2], t2[2];  // passive tracer stages (used when the ensemble has it)
   BndArgs bnd;
   R* ghost0;
   R* ghost1;
+  R* tghost0;  // tau of the inner ghost cells at the two stage times (tracer on)
+  R* tghost1;
   DevClock* clock;
   double* partials;
   int nbx, nby, nbz, planes;
@@ -31,8 +34,10 @@ struct EnsTables {
   int n_runs;
   int n_tiles;          // stage tiles over all runs
   int n_bitems;         // boundary items of 256 columns over all runs
+  int n_titems;         // tracer items of 256 cells over all runs (0: tracer off)
   const int* tile_off;  // [n_runs + 1] prefix sums of tiles
   const int* bnd_off;   // [n_runs + 1] prefix sums of boundary items
+  const int* trc_off;   // [n_runs + 1] prefix sums of tracer items
   GridBar* bar;
   long long spin_limit;
 };
@@ -40,12 +45,12 @@ struct EnsTables {
 struct EnsLaunch {
   const void* runs;  // RunDesc<R>[n_runs] on the device
   EnsTables e;
-  int persistent, grid, nsteps, flux, lim;
+  int persistent, grid, nsteps, flux, lim, tracer;
 };
 
 void launch_ensemble(const EnsLaunch& L, bool f32, hipStream_t s);
 void launch_ens_clock_begin(DevClock* const* clocks, int n, double t_end, hipStream_t s);
 void launch_ens_gather(DevClock* const* clocks, int n, DevClock* out, hipStream_t s);
-int ensemble_blocks_per_cu(bool f32, int flux, int lim);
+int ensemble_blocks_per_cu(bool f32, int flux, int lim, bool tracer);
 
 }  // namespace icr

@@ -92,6 +92,51 @@ struct TracerArgs {
   long long ncell;
 };
 
+// One cell of a passive-tracer stage: upwind rho tau fluxes from the stage's
+// face mass fluxes, then the stage update (stage 2: the RK2 combine with tn).
+template <typename R, int STAGE>
+__device__ __forceinline__ void tracer_cell(const TracerArgs<R>& a, long long c) {
+  if (c >= a.ncell) return;
+  const int nr = a.nr, nt = a.nt, np = a.np;
+  const int i = (int)(c % nr);
+  const long long col = c / nr;
+  const int j = (int)(col % nt), k = (int)(col / nt);
+  if (!a.clock->active) {
+    if (STAGE == 2) a.tout[c] = a.tn[c];
+    return;
+  }
+  const long long n = a.ncell, pc = (long long)nt * nr;
+  auto tau = [&](long long q) { return a.tin[q] / a.rho[q]; };
+  const R tc = tau(c);
+  // r faces i-1/2, i+1/2
+  const R fr0 = a.fm[c];
+  const R fr1 = i + 1 < nr ? a.fm[c + 1] : a.frout[(long long)k * nt + j];
+  const R tr0 = i > 0 ? tau(c - 1) : a.gtau[(long long)k * nt + j];
+  const R tr1 = i + 1 < nr ? tau(c + 1) : tc;
+  const R gr0 = fr0 * (fr0 >= R(0) ? tr0 : tc), gr1 = fr1 * (fr1 >= R(0) ? tc : tr1);
+  // theta faces j-1/2, j+1/2
+  const R ft0 = a.fm[n + c];
+  const R ft1 = j + 1 < nt ? a.fm[n + c + nr] : a.ftend[(long long)k * nr + i];
+  const R tt0 = j > 0 ? tau(c - nr) : tc;
+  const R tt1 = j + 1 < nt ? tau(c + nr) : tc;
+  const R gt0 = ft0 * (ft0 >= R(0) ? tt0 : tc), gt1 = ft1 * (ft1 >= R(0) ? tc : tt1);
+  // phi faces k-1/2, k+1/2 (periodic)
+  const long long cm = c + (k > 0 ? -pc : (long long)(np - 1) * pc);
+  const long long cp = c + (k + 1 < np ? pc : -(long long)(np - 1) * pc);
+  const R fp0 = a.fm[2 * n + c], fp1 = a.fm[2 * n + cp];
+  const R gp0 = fp0 * (fp0 >= R(0) ? tau(cm) : tc), gp1 = fp1 * (fp1 >= R(0) ? tc : tau(cp));
+  const R hr = a.m.hr[i];
+  R L = R(0);
+  L -= (a.m.rp2[i] * gr1 - a.m.rm2[i] * gr0) * a.m.ivr[i];
+  L -= hr * (a.m.sp[j] * gt1 - a.m.sm[j] * gt0) * a.m.ict[j];
+  L -= hr * a.m.phf[j] * (gp1 - gp0);
+  const R dt = (R)a.clock->dt;
+  if (STAGE == 1)
+    a.tout[c] = a.tin[c] + dt * L;
+  else
+    a.tout[c] = R(0.5) * a.tn[c] + R(0.5) * (a.tin[c] + dt * L);
+}
+
 struct ProbeArgs {
   int n, npts, max_probes;
   long long log_rows;

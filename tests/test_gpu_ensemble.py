@@ -1,7 +1,8 @@
 """Batched ensemble on the GPU: every run is bit-identical to the same run
 stepped alone through icr_step, in the persistent (one launch, device-wide
-barriers) and the batched (one launch per phase) modes, and one run is
-checked against the oracle."""
+barriers) and the batched (one launch per phase) modes, also with the HLLD
+flux and with the passive CME tracer (state and tracer bitwise), and one run
+is checked against the oracle."""
 import sys
 
 import numpy as np
@@ -38,10 +39,10 @@ def inputs(q, g):
     return times, maps, cme
 
 
-def build_ensemble(mods, planes):
+def build_ensemble(mods, planes, **phys):
     _, _, ensemble = mods
     grids = [synth.Grid(*s) for s in GRIDS]
-    e = ensemble.Ensemble(grids)
+    e = ensemble.Ensemble(grids, **phys)
     for q, (g, run) in enumerate(zip(grids, e.runs)):
         times, maps, cme = inputs(q, g)
         run.set_maps(times, maps)
@@ -105,3 +106,36 @@ def test_ensemble_grid_size_and_repeat_calls(mods):
     for a, r in zip(ref, e2.runs):
         assert np.array_equal(a, r.get_state(kind=1))
     e2.close()
+
+
+@pytest.mark.parametrize("phys,persistent", [
+    (dict(tracer=True), 1), (dict(tracer=True), 0), (dict(flux=2), 1),
+    (dict(flux=2, limiter=1, tracer=True), 1), (dict(tracer=True, precision=32), 0)])
+def test_ensemble_with_tracer_and_hlld_bitwise_equal_single_runs(mods, phys, persistent):
+    """Every run carries a cone CME; with the tracer on, tau of every run is
+    bit-identical to the single run's as well."""
+    _, solver, _ = mods
+    steps = 19
+    e, grids = build_ensemble(mods, planes=[8, 5, 3], **phys)
+    e.set_mode(persistent, 0, 1)
+    say(f"ensemble {phys}, persistent={persistent}")
+    info = e.step(steps)
+    assert all(i["steps"] == steps and i["status"] == 0 for i in info)
+    n_tau = 0
+    for q, g in enumerate(grids):
+        s = solver.Solver(g, **phys)
+        times, maps, cme = inputs(q, g)
+        s.set_maps(times, maps)
+        s.set_cmes(cme[None])
+        s.init_radial()
+        s.step(steps)
+        a, b = e.runs[q].get_state(kind=1), s.get_state(kind=1)
+        assert np.array_equal(a, b), (q, parity.max_rel(a, b))
+        if phys.get("tracer"):
+            ta, tb = e.runs[q].get_tracer(), s.get_tracer()
+            assert np.array_equal(ta, tb), (q, float(np.max(np.abs(ta - tb))))
+            n_tau += int((ta > 1e-3).sum())
+        s.close()
+    if phys.get("tracer"):
+        assert n_tau > 0  # CME material entered
+    e.close()

@@ -1,7 +1,7 @@
 """GPU parity of the HLLD flux option with the oracle (FP64 bar 1e-9), in
 both stage-kernel variants and both limiters: the tiny static workload and a
 ragged 150 x 30 x 60 grid with a cone CME (fast, rotational and contact waves
-all present); FP32 against FP64; ensembles reject the option."""
+all present); FP32 against FP64.  Ensembles with HLLD: tests/test_gpu_ensemble.py."""
 import sys
 
 import numpy as np
@@ -82,10 +82,3 @@ def test_hlld_fp32_close_to_fp64(mods):
     a.close()
     b.close()
 
-
-def test_ensemble_rejects_hlld(mods):
-    _, _, abi = mods
-    from paper_2501_15923_amd.ensemble import Ensemble
-    with pytest.raises(abi.IcarusError) as e:
-        Ensemble([synth.Grid(64, 16, 32)], flux=HLLD)
-    assert e.value.code == abi.ICR_ERR_UNSUPPORTED

@@ -131,10 +131,3 @@ def test_divv_matches_oracle(mods, orc_run):
     assert scale > 0 and err <= 1e-9 * scale
     s.close()
 
-
-def test_ensemble_rejects_tracer(mods):
-    _, _, abi = mods
-    from paper_2501_15923_amd.ensemble import Ensemble
-    with pytest.raises(abi.IcarusError) as e:
-        Ensemble([synth.Grid(64, 16, 32)], tracer=True)
-    assert e.value.code == abi.ICR_ERR_UNSUPPORTED
