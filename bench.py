@@ -73,6 +73,9 @@ def parse():
     ap.add_argument("--ens-grid", default=None,
                     help="NRxNTxNP: give every ensemble run this grid (default: uneven grids)")
     ap.add_argument("--weights", default=WEIGHTS)
+    ap.add_argument("--launch", default=None, metavar="TILE_R,PLANES",
+                    help="fixed stage-kernel launch shape instead of the launch tuner's "
+                         "choice (counter runs: every stage-2 dispatch then has one shape)")
     return ap.parse_args()
 
 
@@ -572,7 +575,10 @@ def main():
     s = Solver(g, precision=args.precision, probe_log_rows=args.steps + args.warmup + 16,
                max_traj_pts=w.probes.shape[1], tracer=args.tracer, flux=flux, limiter=lim)
     tile_r, planes = 0, 0
-    if args.variant in (0, 2) and not args.tracer and lim != 2:
+    if args.launch:
+        tile_r, planes = (int(v) for v in args.launch.split(","))
+        log(f"bench: fixed launch tile_r {tile_r}, {planes} phi planes per block")
+    elif args.variant in (0, 2) and not args.tracer and lim != 2:
         # the launch tuner's choice for this grid (untimed; timed on a
         # throwaway solver of the same shape)
         from paper_2501_15923_amd import autotune
