@@ -578,7 +578,7 @@ def main():
     if args.launch:
         tile_r, planes = (int(v) for v in args.launch.split(","))
         log(f"bench: fixed launch tile_r {tile_r}, {planes} phi planes per block")
-    elif args.variant in (0, 2) and not args.tracer and lim != 2:
+    elif args.variant in (0, 2) and not args.tracer:
         # the launch tuner's choice for this grid (untimed; timed on a
         # throwaway solver of the same shape)
         from paper_2501_15923_amd import autotune

@@ -58,9 +58,10 @@ def _time(fn, reps):
     return e0.elapsed_time(e1) / reps
 
 
-def solver_candidates(g):
+def solver_candidates(g, limiter=0):
     out = []
-    for tr in (64, 32):
+    # the WENO5 face-once tile exists in the 64-lane shape only
+    for tr in ((64,) if limiter == 2 else (64, 32)):
         for planes in (2, 4, 5, 6, 8, 10, 12, 15, 16):
             if planes <= g.np_:
                 out.append((tr, planes))
@@ -79,7 +80,7 @@ def tune_solver(g, precision=64, flux=0, limiter=0, steps=32, cache=DEFAULT_CACH
     s.init_radial()
     s.step(4 * steps)  # clocks up before the first candidate
     timings = {}
-    for tr, planes in solver_candidates(g):
+    for tr, planes in solver_candidates(g, limiter):
         s.set_launch(2, tr, planes, 1)
         s.step(16)
         timings[f"{tr}x{planes}"] = _time(s.step, steps)

@@ -104,6 +104,10 @@ Layout make_layout(const icr_grid& g, const icr_phys& p) {
     const long long b = stage_lds_blocks(g.n_r, g.n_theta, g.n_phi, tr, 1);
     mb = b > mb ? b : mb;
   }
+  {
+    const long long b = stage_w5_blocks(g.n_r, g.n_theta, g.n_phi, 1);
+    mb = b > mb ? b : mb;
+  }
   L.max_blocks = mb;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -261,6 +265,7 @@ struct icr_solver {
       const dim3 gr = grid();
       return (int)(gr.x * gr.y * gr.z);
     }
+    if (p.limiter == ICR_LIM_WENO5) return (int)stage_w5_blocks(g.n_r, g.n_theta, g.n_phi, planes);
     return (int)stage_lds_blocks(g.n_r, g.n_theta, g.n_phi, tile_r, planes);
   }
 
@@ -356,12 +361,16 @@ struct icr_solver {
     const StageArgs<R> a2 = stage_args<R>(2, from, to, 1);
     if (variant == 1)
       launch_stage<R>(a1, 1, p.flux, p.limiter, grid(), block(), st);
+    else if (p.limiter == ICR_LIM_WENO5)
+      launch_stage_w5<R>(a1, 1, p.flux, planes, st);
     else
       launch_stage_lds<R>(a1, 1, p.flux, p.limiter, tile_r, planes, st);
     if (trc()) launch_tracer<R>(tracer_args<R>(from, from, from, 2, 0), 1, st);
     if (ev) (void)hipEventRecord(ev[2], st);
     if (variant == 1)
       launch_stage<R>(a2, 2, p.flux, p.limiter, grid(), block(), st);
+    else if (p.limiter == ICR_LIM_WENO5)
+      launch_stage_w5<R>(a2, 2, p.flux, planes, st);
     else
       launch_stage_lds<R>(a2, 2, p.flux, p.limiter, tile_r, planes, st);
     if (trc()) launch_tracer<R>(tracer_args<R>(2, 2, from, to, 1), 2, st);
@@ -505,7 +514,9 @@ int icr_create(const icr_grid* g, const icr_phys* p, void* ws, size_t ws_bytes, 
   s->gm = p->gravity ? kGM / (s->un.len * s->un.v * s->un.v) : 0.0;
   s->dph = 2.0 * kPi / g->n_phi;
   s->tile_r = 64;
-  s->variant = p->limiter == ICR_LIM_WENO5 ? 1 : 2;  // WENO5: thread-per-cell kernel only
+  // WENO5 with the tracer: the thread-per-cell kernel (the WENO5 face-once
+  // tile keeps no face mass fluxes)
+  s->variant = (p->limiter == ICR_LIM_WENO5 && p->tracer) ? 1 : 2;
   s->planes = 8;
   s->use_graphs = 1;
   s->graphs_ok = false;
@@ -1165,9 +1176,12 @@ int icr_fast_math(const double* x, long long n, double* rcp, double* sq, void* s
 int icr_set_launch(icr_solver* s, int variant, int tile_r, int planes, int use_graphs) {
   if (!s) return fail(ICR_ERR_ARG, "solver is NULL");
   if (variant == 0) variant = 2;
-  if (s->p.limiter == ICR_LIM_WENO5) {  // the face-once kernel has a 2-cell halo
-    variant = 1;
-    if (tile_r != 64 && tile_r != 128 && tile_r != 256) tile_r = 64;
+  if (s->p.limiter == ICR_LIM_WENO5) {
+    // the WENO5 face-once tile is 64 x 4; with the tracer only the
+    // thread-per-cell kernel runs WENO5
+    if (s->trc()) variant = 1;
+    if (variant == 1 && tile_r != 64 && tile_r != 128 && tile_r != 256) tile_r = 64;
+    if (variant == 2) tile_r = 64;
   }
   if (variant != 1 && variant != 2) return fail(ICR_ERR_ARG, "variant must be 0, 1 or 2");
   if (tile_r == 0) tile_r = 64;

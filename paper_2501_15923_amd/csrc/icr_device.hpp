@@ -221,7 +221,7 @@ __device__ __forceinline__ void reconstruct(const R (&a)[NV], const R (&b)[NV],
 // at, centred on and starting at c, weighted by d_k / (eps + beta_k)^2 with
 // linear weights (1, 6, 3)/10 and smoothness indicators beta_k; eps is 1e-6
 // of the stencil's mean square (plus 1e-40), so the weights are free of units.
-template <typename R>
+template <typename R, bool FAST = false>
 __device__ __forceinline__ R weno5(R a, R b, R c, R d, R e) {
   constexpr R sixth = R(1) / R(6);
   const R q0 = (R(2) * a - R(7) * b + R(11) * c) * sixth;
@@ -241,6 +241,7 @@ __device__ __forceinline__ R weno5(R a, R b, R c, R d, R e) {
     // weights d_k / g_k scaled by g0 g1 g2: one division (products stay in
     // range in FP64: g >= 1e-80)
     const R a0 = R(0.1) * g1 * g2, a1 = R(0.6) * g0 * g2, a2 = R(0.3) * g0 * g1;
+    if constexpr (FAST) return (a0 * q0 + a1 * q1 + a2 * q2) * rcp_fast(a0 + a1 + a2);
     return (a0 * q0 + a1 * q1 + a2 * q2) / (a0 + a1 + a2);
   } else {
     const R a0 = R(0.1) / g0, a1 = R(0.6) / g1, a2 = R(0.3) / g2;
@@ -250,15 +251,15 @@ __device__ __forceinline__ R weno5(R a, R b, R c, R d, R e) {
 
 // WENO5 face states of face m-1/2 from the six cells m-3 .. m+2 (p0..p5);
 // a face state with rho or p <= 0 falls back to its cell value.
-template <typename R>
+template <typename R, bool FAST = false>
 __device__ __forceinline__ void reconstruct_weno5(const R (&p0)[NV], const R (&p1)[NV],
                                                   const R (&p2)[NV], const R (&p3)[NV],
                                                   const R (&p4)[NV], const R (&p5)[NV],
                                                   R (&wl)[NV], R (&wr)[NV]) {
 #pragma unroll
   for (int v = 0; v < NV; ++v) {
-    wl[v] = weno5<R>(p0[v], p1[v], p2[v], p3[v], p4[v]);
-    wr[v] = weno5<R>(p5[v], p4[v], p3[v], p2[v], p1[v]);
+    wl[v] = weno5<R, FAST>(p0[v], p1[v], p2[v], p3[v], p4[v]);
+    wr[v] = weno5<R, FAST>(p5[v], p4[v], p3[v], p2[v], p1[v]);
   }
   if (!(wl[0] > R(0) && wl[4] > R(0)))
 #pragma unroll

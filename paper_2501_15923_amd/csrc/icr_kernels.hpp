@@ -415,6 +415,10 @@ void launch_stage_lds(const StageArgs<R>& a, int stage, int flux, int lim, int t
 // each side carry the r halo.
 __host__ __device__ constexpr int tile_cells_r(int tile_r) { return tile_r - 4; }
 long long stage_lds_blocks(int nr, int nt, int np, int tile_r, int kplanes);
+// the WENO5 face-once tile (64 x 4 threads, three-cell halo)
+long long stage_w5_blocks(int nr, int nt, int np, int kplanes);
+template <typename R>
+void launch_stage_w5(const StageArgs<R>& a, int stage, int flux, int kplanes, hipStream_t s);
 // rcp_fast / sqrt_fast of n doubles (accuracy diagnostics)
 void launch_fast_math(const double* x, long long n, double* rcp, double* sq, hipStream_t s);
 template <typename R>

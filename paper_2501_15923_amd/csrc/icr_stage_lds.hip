@@ -1,6 +1,7 @@
 // icr_stage_lds.hip -- single-run launches of the face-once stage kernel
 // and the finalize kernel (device code in icr_stage_lds.hpp).
 #include "icr_stage_lds.hpp"
+#include "icr_stage_w5.hpp"
 
 namespace icr {
 
@@ -69,6 +70,45 @@ template void launch_stage_lds<double>(const StageArgs<double>&, int, int, int, 
                                        hipStream_t);
 template void launch_stage_lds<float>(const StageArgs<float>&, int, int, int, int, int,
                                       hipStream_t);
+
+// WENO5: the face-once tile with a three-cell halo (64 x 4 threads, 58
+// cells along r per row)
+template <typename R, int FLUX, int STAGE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(ICR_LDS_WAVES)))
+k_stage_w5(StageArgs<R> a, int kplanes) {
+  const int nbx = gridDim.x, nby = gridDim.y;
+  const int nb = nbx * nby * gridDim.z;
+  const int b = (blockIdx.z * nby + blockIdx.y) * nbx + blockIdx.x;
+  const int tile = xcd_tile(b, nb);
+  __shared__ StageW5<R> sm;
+  stage_tile_w5<R, FLUX, STAGE>(a, kplanes, tile % nbx, (tile / nbx) % nby, tile / (nbx * nby),
+                                tile, sm);
+}
+
+template <typename R, int FLUX>
+static void launch_w5_t(const StageArgs<R>& a, int stage, int kplanes, hipStream_t s) {
+  const dim3 grid((a.nr + W5_TI - 1) / W5_TI, (a.nt + W5_TT - 1) / W5_TT,
+                  (a.np + kplanes - 1) / kplanes);
+  const dim3 blk(W5_TR, W5_TT);
+  if (stage == 1)
+    hipLaunchKernelGGL((k_stage_w5<R, FLUX, 1>), grid, blk, 0, s, a, kplanes);
+  else
+    hipLaunchKernelGGL((k_stage_w5<R, FLUX, 2>), grid, blk, 0, s, a, kplanes);
+}
+
+template <typename R>
+void launch_stage_w5(const StageArgs<R>& a, int stage, int flux, int kplanes, hipStream_t s) {
+  if (flux == FLUX_TVDLF) launch_w5_t<R, FLUX_TVDLF>(a, stage, kplanes, s);
+  else if (flux == FLUX_HLLD) launch_w5_t<R, FLUX_HLLD>(a, stage, kplanes, s);
+  else launch_w5_t<R, FLUX_HLL>(a, stage, kplanes, s);
+}
+template void launch_stage_w5<double>(const StageArgs<double>&, int, int, int, hipStream_t);
+template void launch_stage_w5<float>(const StageArgs<float>&, int, int, int, hipStream_t);
+
+long long stage_w5_blocks(int nr, int nt, int np, int kplanes) {
+  return (long long)((nr + W5_TI - 1) / W5_TI) * ((nt + W5_TT - 1) / W5_TT) *
+         ((np + kplanes - 1) / kplanes);
+}
 
 long long stage_lds_blocks(int nr, int nt, int np, int tile_r, int kplanes) {
   const int tt = 256 / tile_r, ti = tile_cells_r(tile_r);

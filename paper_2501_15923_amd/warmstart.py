@@ -117,10 +117,11 @@ def build_dataset(net, grid, seeds, t_ref, rc, thc, precision=64, batch=64):
 
 
 def scale_output(params, dims, s):
-    """Scale the last layer's weights and biases of output variable v (the
-    output index is r * 8 + v) by s[v].  Training on targets scaled the same
-    way weights the squared error of variable v by s[v]^2 (the last layer is
-    linear); dividing by s afterwards returns the usual output."""
+    """Scale the last layer's weights and biases of output r * 8 + v by s[v]
+    (s of length 8) or by s[r * 8 + v] (length 8 n_r).  Training on targets
+    scaled the same way weights the squared error of that output by s^2 (the
+    last layer is linear); dividing by s afterwards returns the usual
+    output."""
     nt, nph, nr, c1, c2, hidden, lo, hi = (int(d) for d in dims)
     k1 = 3 * (hi - lo + 1) * 8
     no = 8 * nr
@@ -128,7 +129,8 @@ def scale_output(params, dims, s):
     off = k1 * c1 + c1 + 9 * c1 * c2 + c2 + c2 * hidden + hidden
     W4 = p[off:off + hidden * no].reshape(hidden, no)
     b4 = p[off + hidden * no:off + hidden * no + no]
-    col = np.tile(np.asarray(s, dtype=np.float32), nr)
+    s = np.asarray(s, dtype=np.float32)
+    col = np.tile(s, nr) if s.size == 8 else s
     W4 *= col[None, :]
     b4 *= col
     assert off + hidden * no + no == p.size
@@ -272,6 +274,10 @@ def main(argv=None):
     ap.add_argument("--out", default=None)
     ap.add_argument("--weights", default=None, help="evaluate these weights (skip training)")
     ap.add_argument("--report", default=None)
+    ap.add_argument("--outer-weight", type=float, default=1.0,
+                    help="loss weight of every output beyond --outer-au (the 1 AU shell "
+                         "criterion never sees them; they only feed the residual)")
+    ap.add_argument("--outer-au", type=float, default=1.05)
     ap.add_argument("--rho-weight", type=float, default=1.0,
                     help="loss weight of the density output (targets and the output layer "
                          "scaled by its square root while training)")
@@ -317,19 +323,23 @@ def main(argv=None):
         if not args.no_ablations:
             mean_t = T.mean(dim=0)
         p_init = np.load(args.init_weights)["params"] if args.init_weights else p0
-        osc = np.ones(8)
-        osc[0] = math.sqrt(args.rho_weight)
-        if args.rho_weight != 1.0:
-            T[..., 0::8] *= float(osc[0])
+        osc = np.ones(8 * g.nr)
+        osc[0::8] = math.sqrt(args.rho_weight)
+        rc_au = rc.cpu().numpy() / synth.AU
+        osc.reshape(g.nr, 8)[rc_au > args.outer_au] *= math.sqrt(args.outer_weight)
+        weighted = args.rho_weight != 1.0 or args.outer_weight != 1.0
+        if weighted:
+            T *= torch.from_numpy(osc.astype(np.float32)).cuda()
             p_init = scale_output(p_init, net.dims, osc)
         net.set_params(p_init)
         report["init_weights"] = args.init_weights
         report["rho_weight"] = args.rho_weight
+        report["outer_weight"] = [args.outer_weight, args.outer_au]
         report["train_samples"] = int(X.shape[0])
         hist, tsec = train(net, X, T, args.epochs, lr=args.lr)
         report.update(train_loss=hist, train_seconds=tsec)
         p = net.get_params()
-        if args.rho_weight != 1.0:
+        if weighted:
             p = scale_output(p, net.dims, 1.0 / osc)
         if args.out:
             extra = {} if mean_t is None else {"mean_target": mean_t.cpu().numpy()}

@@ -1,8 +1,11 @@
-"""GPU parity of the WENO5 reconstruction (three ghost layers, thread-per-cell
-stage kernel) with the oracle at the FP64 bar 1e-9: the tiny static workload
-with the TVDLF and HLLD fluxes, and a ragged 150 x 30 x 60 grid with a cone
-CME; FP32 against FP64; a request for the face-once kernel still runs the
-thread-per-cell one; ensembles reject WENO5."""
+"""GPU parity of the WENO5 reconstruction (three ghost layers) with the
+oracle at the FP64 bar 1e-9, in both stage kernels (the face-once tile with
+a three-cell halo, the default, and the thread-per-cell kernel): the tiny
+static workload with the TVDLF and HLLD fluxes, a ragged 150 x 30 x 60 grid
+with a cone CME, odd and minimal radial sizes and the asymm inner rule; the
+face-once tile gives the same bits for every phi chunking and agrees with
+the thread-per-cell kernel to rounding; FP32 against FP64; ensembles reject
+WENO5."""
 import sys
 
 import numpy as np
@@ -30,11 +33,15 @@ def mods():
     return oracle, solver, _abi
 
 
-def pair(mods, g, times, maps, cmes=None, flux=0, precision=64):
+def pair(mods, g, times, maps, cmes=None, flux=0, precision=64, variant=2, planes=0,
+         bc_transverse=0):
     oracle, solver, _ = mods
-    s = solver.Solver(g, flux=flux, limiter=WENO5, precision=precision)
+    s = solver.Solver(g, flux=flux, limiter=WENO5, precision=precision,
+                      bc_transverse=bc_transverse)
+    s.set_launch(variant, 64, planes or min(8, g.np_), 1)
     o = oracle.Oracle(g.nr, g.nt, g.np_, flux=flux, limiter=WENO5, r_in=g.r_in,
-                      r_out=g.r_out, th_min=g.th_min, th_max=g.th_max)
+                      r_out=g.r_out, th_min=g.th_min, th_max=g.th_max,
+                      bc_transverse=bc_transverse)
     for x in (s, o):
         x.set_maps(times, maps)
         if cmes is not None:
@@ -43,45 +50,77 @@ def pair(mods, g, times, maps, cmes=None, flux=0, precision=64):
     return s, o
 
 
-@pytest.mark.parametrize("flux", [0, 2])
-def test_weno5_tiny_static(mods, flux):
+@pytest.mark.parametrize("flux,variant", [(0, 2), (2, 2), (0, 1), (2, 1)])
+def test_weno5_tiny_static(mods, flux, variant):
     oracle = mods[0]
     w = configs.tiny_static()
-    say(f"WENO5 tiny static, flux {flux}")
-    s, o = pair(mods, w.grid, w.times, w.maps, flux=flux)
+    say(f"WENO5 tiny static, flux {flux}, variant {variant}")
+    s, o = pair(mods, w.grid, w.times, w.maps, flux=flux, variant=variant)
     s.step(100)
     o.step(100)
     parity.assert_parity(s.get_state(kind=1), o.get_state(kind=oracle.CONS_CODE))
     s.close()
 
 
-def test_weno5_ragged_grid_with_cme(mods):
+@pytest.mark.parametrize("variant", [2, 1])
+def test_weno5_ragged_grid_with_cme(mods, variant):
     oracle = mods[0]
     g = synth.Grid(150, 30, 60)
     times, maps = synth.dynamic_maps(g, 6, n_maps=3, cadence=3600.0)
     earth = synth.orbit_table(3 * synth.DAY, 600.0, synth.AU, 0.0, 0.9)
     cme = synth.cone_cme(8, earth, t_start=0.0, duration=6 * synth.HOUR, speed=1400e3)
-    say("WENO5 + HLLD 150x30x60 with CME, 30 steps")
-    s, o = pair(mods, g, times, maps, cmes=cme[None], flux=2)
+    say(f"WENO5 + HLLD 150x30x60 with CME, 30 steps, variant {variant}")
+    s, o = pair(mods, g, times, maps, cmes=cme[None], flux=2, variant=variant)
     s.step(30)
     o.step(30)
     parity.assert_parity(s.get_state(kind=1), o.get_state(kind=oracle.CONS_CODE))
     s.close()
 
 
-def test_weno5_fp32_and_launch_request(mods):
+@pytest.mark.parametrize("shape,bct", [((3, 5, 4), 1), ((59, 6, 7), 0), ((61, 9, 5), 1),
+                                       ((1, 4, 6), 0), ((117, 3, 8), 0)])
+def test_weno5_face_once_odd_grids_and_asymm(mods, shape, bct):
+    """Radial sizes around the 58-cell tile (59, 61, 117), the minimum (1;
+    asymm needs 3), fewer colatitude rows than the tile, the asymm rule."""
+    oracle = mods[0]
+    g = synth.Grid(*shape)
+    times, maps = synth.dynamic_maps(g, 9, n_maps=2, cadence=3600.0)
+    say(f"WENO5 face-once grid {shape} bc_transverse {bct}")
+    s, o = pair(mods, g, times, maps, bc_transverse=bct)
+    s.step(30)
+    o.step(30)
+    parity.assert_parity(s.get_state(kind=1), o.get_state(kind=oracle.CONS_CODE),
+                         what=f"weno5 {shape}")
+    s.close()
+
+
+def test_weno5_face_once_chunking_bitwise_and_variants_agree(mods):
+    g = synth.Grid(150, 30, 20)
+    times, maps = synth.dynamic_maps(g, 3, cadence=3600.0)
+    out = []
+    for planes in (8, 1, 7, 20):
+        s, _ = pair(mods, g, times, maps, planes=planes)
+        s.step(23)
+        out.append(s.get_state(kind=1))
+        s.close()
+    for a in out[1:]:
+        assert np.array_equal(out[0], a)
+    v1, _ = pair(mods, g, times, maps, variant=1)
+    v1.step(23)
+    assert parity.max_rel(v1.get_state(kind=1), out[0]) < 1e-12
+    v1.close()
+
+
+def test_weno5_fp32_close_to_fp64(mods):
     w = configs.tiny_static()
     a, _ = pair(mods, w.grid, w.times, w.maps)
     b, _ = pair(mods, w.grid, w.times, w.maps, precision=32)
-    c, _ = pair(mods, w.grid, w.times, w.maps)
-    c.set_launch(2, 32, 4, 1)  # face-once requested: WENO5 still runs thread-per-cell
-    for x in (a, b, c):
+    for x in (a, b):
         x.step(60)
     e = parity.max_rel(b.get_state(kind=1), a.get_state(kind=1))
     say(f"WENO5 fp32 vs fp64 after 60 steps: {e:.3e}")
     assert e < 1e-3
-    assert np.array_equal(a.get_state(kind=1), c.get_state(kind=1))
-    for x in (a, b, c):
+    for x in (a, b):
         x.close()
 
 
