@@ -383,6 +383,113 @@ __global__ void __launch_bounds__(256) k_amr_stage(AmrArgs a, const int* __restr
   }
 }
 
+// Face-once variant for leaves of at most 512 cells (two per thread): the
+// faces of one direction at a time go to LDS (each computed once by
+// amr_face, the same function and inputs as above, so the results are
+// bitwise those of k_amr_stage), then every thread adds them to the
+// right-hand sides of its cells, kept in registers.  Face index along
+// direction d: position p in [0, b_d] (between cells p-1 and p) fastest for
+// r, then the transverse cells.
+constexpr int AMR_FO_CELLS = 512;
+template <int FLUX, int LIM>
+__global__ void __launch_bounds__(256) k_amr_stage_fo(AmrArgs a, const int* __restrict__ list,
+                                                      int stage) {
+  extern __shared__ double sF[];  // [NA][faces of one direction]
+  if (!a.clock->active) return;
+  const int slot = list[blockIdx.x];
+  const int* key = a.key + 4 * slot;
+  const int l = key[0];
+  const AmrLevel& LV = a.lv[l];
+  const Metric<double>& m = LV.m;
+  const double dt = a.clock->dt;
+  const double* in = stage == 1 ? a.U : a.U1;
+  double* out = stage == 1 ? a.U1 : a.U;
+  const int br = a.br, bt = a.bt, bp = a.bp;
+  const int ncell = br * bt * bp;
+  const int nfmax = (br + 1) * bt * bp > br * (bt + 1) * bp
+                        ? ((br + 1) * bt * bp > br * bt * (bp + 1) ? (br + 1) * bt * bp
+                                                                  : br * bt * (bp + 1))
+                        : (br * (bt + 1) * bp > br * bt * (bp + 1) ? br * (bt + 1) * bp
+                                                                  : br * bt * (bp + 1));
+  double L[2][NA];
+  for (int q = 0; q < 2; ++q)
+    for (int v = 0; v < NA; ++v) L[q][v] = 0.0;
+  for (int d = 0; d < 3; ++d) {
+    const int nf = d == 0 ? (br + 1) * bt * bp : (d == 1 ? br * (bt + 1) * bp : br * bt * (bp + 1));
+    for (int f = threadIdx.x; f < nf; f += blockDim.x) {
+      int p, ci, cj, ck;  // face position along d and the transverse cells
+      if (d == 0) {
+        p = f % (br + 1);
+        cj = (f / (br + 1)) % bt;
+        ck = f / ((br + 1) * bt);
+        ci = p;
+      } else if (d == 1) {
+        ci = f % br;
+        p = (f / br) % (bt + 1);
+        ck = f / (br * (bt + 1));
+        cj = p;
+      } else {
+        ci = f % br;
+        cj = (f / br) % bt;
+        p = f / (br * bt);
+        ck = p;
+      }
+      double fl[NA];
+      amr_face<FLUX, LIM>(a, in, slot, d, AG + ck, AG + cj, AG + ci, fl);
+      for (int v = 0; v < NA; ++v) sF[v * nfmax + f] = fl[v];
+      const int bd = d == 0 ? br : (d == 1 ? bt : bp);
+      if (p == 0 || p == bd) {  // block face: kept for the flux correction
+        const int q = d == 0 ? ck * bt + cj : (d == 1 ? ck * br + ci : cj * br + ci);
+        for (int v = 0; v < NA; ++v) a.F[fidx(a, slot, 2 * d + (p == bd), v, q)] = fl[v];
+      }
+    }
+    __syncthreads();
+    for (int q = 0; q < 2; ++q) {
+      const int c = threadIdx.x + q * blockDim.x;
+      if (c >= ncell) break;
+      const int ci = c % br, cj = (c / br) % bt, ck = c / (br * bt);
+      const int gi = key[1] * br + ci, gj = key[2] * bt + cj;
+      if (d == 0) {
+        const int f0 = (ck * bt + cj) * (br + 1) + ci;
+        for (int v = 0; v < NA; ++v)
+          L[q][v] -= (m.rp2[gi] * sF[v * nfmax + f0 + 1] - m.rm2[gi] * sF[v * nfmax + f0]) *
+                     m.ivr[gi];
+      } else if (d == 1) {
+        const int f0 = (ck * (bt + 1) + cj) * br + ci;
+        for (int v = 0; v < NA; ++v)
+          L[q][v] -= m.hr[gi] *
+                     (m.sp[gj] * sF[v * nfmax + f0 + br] - m.sm[gj] * sF[v * nfmax + f0]) *
+                     m.ict[gj];
+      } else {
+        const int f0 = (ck * bt + cj) * br + ci;
+        const double fph = m.hr[gi] * m.phf[gj];
+        for (int v = 0; v < NA; ++v)
+          L[q][v] -= fph * (sF[v * nfmax + f0 + br * bt] - sF[v * nfmax + f0]);
+      }
+    }
+    __syncthreads();  // the next direction overwrites sF
+  }
+  for (int q = 0; q < 2; ++q) {
+    const int c = threadIdx.x + q * blockDim.x;
+    if (c >= ncell) break;
+    const int ci = c % br, cj = (c / br) % bt, ck = c / (br * bt);
+    const int ii = AG + ci, jj = AG + cj, kk = AG + ck;
+    const int gi = key[1] * br + ci, gj = key[2] * bt + cj;
+    double u[NV], w[NV];
+    for (int v = 0; v < NV; ++v) u[v] = in[pidx(a, slot, v, kk, jj, ii)];
+    cons2prim<double>(u, w, a.gm1);
+    double Ls[NV];
+    for (int v = 0; v < NV; ++v) Ls[v] = L[q][v];
+    add_sources<double>(w, m, gi, gj, a.omega, a.gravity, a.corot, Ls);
+    for (int v = 0; v < NV; ++v) L[q][v] = Ls[v];
+    for (int v = 0; v < NA; ++v) {
+      const long long o = pidx(a, slot, v, kk, jj, ii);
+      const double uc = in[o];
+      out[o] = stage == 1 ? uc + dt * L[q][v] : 0.5 * out[o] + 0.5 * (uc + dt * L[q][v]);
+    }
+  }
+}
+
 // --------------------------------------------------------- flux correction --
 // One thread per (listed face of direction d, face cell): the list holds
 // 2 slot + side of the coarse leaf faces whose neighbour region holds finer
@@ -930,7 +1037,14 @@ struct icr_amr {
 
   template <int FLUX, int LIM>
   void launch_stage_t(const AmrArgs& a, int* d, int n, int stage) {
-    hipLaunchKernelGGL((k_amr_stage<FLUX, LIM>), dim3(n), dim3(256), 0, stream, a, d, stage);
+    const int br = q.block_r, bt = q.block_theta, bp = q.block_phi;
+    const int nf = std::max((br + 1) * bt * bp, std::max(br * (bt + 1) * bp, br * bt * (bp + 1)));
+    const size_t lds = sizeof(double) * NA * (size_t)nf;
+    if (br * bt * bp <= AMR_FO_CELLS && lds <= 48 * 1024)
+      hipLaunchKernelGGL((k_amr_stage_fo<FLUX, LIM>), dim3(n), dim3(256), lds, stream, a, d,
+                         stage);
+    else
+      hipLaunchKernelGGL((k_amr_stage<FLUX, LIM>), dim3(n), dim3(256), 0, stream, a, d, stage);
   }
   void launch_stage(const AmrArgs& a, int* d, int n, int stage) {
     const int f = p.flux, lm = p.limiter;
