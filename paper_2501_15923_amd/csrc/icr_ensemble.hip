@@ -49,7 +49,7 @@ __device__ bool grid_sync(GridBar* gb, unsigned nblocks, long long spin_limit) {
     } else {
       long long n = 0;
       while (__hip_atomic_load(&gb->gen, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == g) {
-        __builtin_amdgcn_s_sleep(2);
+        __builtin_amdgcn_s_sleep(32);  // ~2000 cycles between polls of the shared line
         if (++n > spin_limit) {
           atomicExch(&gb->error, 1);
           ok = 0;
