@@ -18,6 +18,7 @@ from __future__ import annotations
 import argparse
 import json
 import math
+import os
 import sys
 import time
 
@@ -137,6 +138,74 @@ def scale_output(params, dims, s):
     return p
 
 
+def widen_params(params, dims, c1, c2, hidden, seed=0):
+    """Grow the encoder channels and the decoder width without changing the
+    network's function: the new units get random incoming weights (the
+    spread of the existing ones, zero biases) and zero outgoing weights, so
+    every output is unchanged until training moves them.  Returns (params,
+    dims) of the wider network."""
+    nt, nph, nr, a1, a2, ah, lo, hi = (int(d) for d in dims)
+    assert c1 >= a1 and c2 >= a2 and hidden >= ah
+    rng = np.random.default_rng(seed)
+    k1 = 3 * (hi - lo + 1) * 8
+    no = 8 * nr
+    p = np.asarray(params, dtype=np.float32)
+    shapes = [(k1, a1), (a1,), (9, a1, a2), (a2,), (a2, ah), (ah,), (ah, no), (no,)]
+    old, o = [], 0
+    for sh in shapes:
+        n = int(np.prod(sh))
+        old.append(p[o:o + n].reshape(sh))
+        o += n
+    assert o == p.size, "parameter vector does not match dims"
+    W1, b1, W2, b2, W3, b3, W4, b4 = old
+
+    def grow(w, shape, fill_std):
+        out = (rng.normal(0.0, fill_std, shape) if fill_std > 0 else np.zeros(shape))
+        out = out.astype(np.float32)
+        out[tuple(slice(0, s) for s in w.shape)] = w
+        return out
+    nW1 = grow(W1, (k1, c1), float(W1.std()))
+    nb1 = grow(b1, (c1,), 0.0)
+    nW2 = grow(W2, (9, c1, c2), float(W2.std()))
+    nW2[:, a1:, :] = 0.0          # new first-layer channels feed nothing yet
+    nb2 = grow(b2, (c2,), 0.0)
+    nW3 = grow(W3, (c2, hidden), float(W3.std()))
+    nW3[a2:, :] = 0.0             # new second-layer channels feed nothing yet
+    nb3 = grow(b3, (hidden,), 0.0)
+    nW4 = grow(W4, (hidden, no), 0.0)  # new decoder units feed nothing yet
+    q = np.concatenate([a.ravel() for a in (nW1, nb1, nW2, nb2, nW3, nb3, nW4, b4)])
+    return q.astype(np.float32), (nt, nph, nr, c1, c2, hidden, lo, hi)
+
+
+class PlainCache:
+    """Plain relaxations (reference shell, steps, wall time) of held-out maps
+    kept in an .npz file, so that repeated evaluations of different weights
+    on the same maps and grid step each plain run once."""
+
+    def __init__(self, path, grid, t_ref):
+        self.path, self.key = path, f"{grid.nr}x{grid.nt}x{grid.np_}_{t_ref:.6e}"
+        self.ref, self.meta = {}, {}
+        if path and os.path.exists(path):
+            z = np.load(path)
+            meta = json.loads(str(z["meta"]))
+            if meta.get("key") == self.key:
+                self.meta = {int(k): v for k, v in meta["runs"].items()}
+                self.ref = {s: z[f"ref_{s}"] for s in self.meta}
+
+    def get(self, seed):
+        if seed not in self.meta:
+            return None
+        return dict(self.meta[seed], ref=self.ref[seed])
+
+    def put(self, seed, plain):
+        self.meta[seed] = {k: v for k, v in plain.items() if k != "ref"}
+        self.ref[seed] = np.asarray(plain["ref"])
+        if self.path:
+            meta = json.dumps({"key": self.key, "runs": self.meta}, default=float)
+            np.savez(self.path, meta=np.array(meta),
+                     **{f"ref_{s}": r for s, r in self.ref.items()})
+
+
 def default_window(grid, v_slow=350e3):
     """First-layer longitude offsets reaching the footpoint of slow wind at the
     outer radius: Omega (r_out - r_in) / v_slow, in cells, plus one; two
@@ -172,9 +241,10 @@ def train(net, X, T, epochs=30, batch=8, lr=2e-3, seed=0):
     return hist, time.perf_counter() - t0
 
 
-def evaluate(net, grid, seeds, t_ref, predictors, chunk=50, precision=64):
+def evaluate(net, grid, seeds, t_ref, predictors, chunk=50, precision=64, cache=None):
     """Plain vs warm relaxation on held-out maps.  predictors: name ->
-    function(X [1][nt][np][8]) -> y [ncol][no] device tensor."""
+    function(X [1][nt][np][8]) -> y [ncol][no] device tensor.  cache: a
+    PlainCache whose stored plain runs are reused (and new ones added)."""
     import torch
 
     from .solver import Solver
@@ -195,7 +265,12 @@ def evaluate(net, grid, seeds, t_ref, predictors, chunk=50, precision=64):
         solver.set_maps(np.zeros(1), m[None])
         solver.init_radial()
         rc, thc = grid_geometry(solver)
-        plain = relax.plain_with_reference(solver, t_ref, chunk, progress=ticker(f"seed {s} plain"))
+        plain = cache.get(s) if cache is not None else None
+        if plain is None:
+            plain = relax.plain_with_reference(solver, t_ref, chunk,
+                                               progress=ticker(f"seed {s} plain"))
+            if cache is not None:
+                cache.put(s, plain)
         row = dict(seed=s, plain=dict((k, v) for k, v in plain.items() if k != "ref"))
         dm = torch.from_numpy(m).cuda()
         for name, pred in predictors.items():
@@ -281,6 +356,12 @@ def main(argv=None):
     ap.add_argument("--rho-weight", type=float, default=1.0,
                     help="loss weight of the density output (targets and the output layer "
                          "scaled by its square root while training)")
+    ap.add_argument("--widen", default=None, metavar="C1,C2,HIDDEN",
+                    help="grow the --init-weights network to these widths first (same "
+                         "function at the start, see widen_params)")
+    ap.add_argument("--plain-cache", default=None,
+                    help=".npz of plain runs of held-out maps: reused when present, "
+                         "extended otherwise")
     ap.add_argument("--no-ablations", action="store_true",
                     help="evaluate the trained network only (no untrained / mean-state starts)")
     args = ap.parse_args(argv)
@@ -295,9 +376,13 @@ def main(argv=None):
     hi = hi if args.phi_hi is None else args.phi_hi
     dims = (g.nt, g.np_, g.nr, args.c1, args.c2, args.hidden, lo, hi)
     src = args.weights or args.init_weights
+    p_widened = None
     if src:
         dims = tuple(int(v) for v in np.load(src)["dims"])
         assert dims[:3] == (g.nt, g.np_, g.nr), "weights for another grid"
+        if args.widen and not args.weights:
+            w1, w2, wh = (int(v) for v in args.widen.split(","))
+            p_widened, dims = widen_params(np.load(src)["params"], dims, w1, w2, wh)
     net = WarmStartNet(*dims[:6], batch_max=8, phi_lo=dims[6], phi_hi=dims[7])
     p0 = init_params(*net.dims, seed=0)
     probe = Solver(g)
@@ -323,6 +408,9 @@ def main(argv=None):
         if not args.no_ablations:
             mean_t = T.mean(dim=0)
         p_init = np.load(args.init_weights)["params"] if args.init_weights else p0
+        if p_widened is not None:
+            p_init = p_widened
+        report["widen"] = args.widen
         osc = np.ones(8 * g.nr)
         osc[0::8] = math.sqrt(args.rho_weight)
         rc_au = rc.cpu().numpy() / synth.AU
@@ -363,7 +451,8 @@ def main(argv=None):
             json.dump(report, open(args.report, "w"), indent=1, default=float)
         return report
     test_seeds = list(range(args.test_seed0, args.test_seed0 + args.test))
-    rows = evaluate(net, g, test_seeds, t_ref, preds)
+    cache = PlainCache(args.plain_cache, g, t_ref) if args.plain_cache else None
+    rows = evaluate(net, g, test_seeds, t_ref, preds, cache=cache)
     report["summary"] = summarise(rows, list(preds))
     report["rows"] = rows
     log(json.dumps(report["summary"], indent=1))

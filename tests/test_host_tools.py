@@ -120,3 +120,57 @@ def test_summarise_ratios_over_converged_runs():
     assert s["converged"] == 2 and s["of"] == 3
     assert abs(s["wall_ratio_median"] - 0.4) < 1e-12 and abs(s["wall_ratio_mean"] - 0.4) < 1e-12
     assert s["steps_median"] == 450.0 and s["plain_steps_median"] == 1100.0
+
+
+def test_widened_network_keeps_its_function_and_trains_every_new_weight():
+    """widen_params adds encoder channels and decoder units whose outgoing
+    weights are zero: the oracle's forward pass gives the same outputs, and
+    the oracle's gradient reaches the new weights (the first step can move
+    them)."""
+    sys.path.insert(0, os.path.join(ROOT, "oracle"))
+    import nn_oracle as O
+    from paper_2501_15923_amd.nn import init_params
+    from paper_2501_15923_amd.warmstart import widen_params
+    dims = (5, 8, 4, 3, 4, 6, -1, 2)
+    p = init_params(*dims[:6], phi_lo=dims[6], phi_hi=dims[7], seed=3)
+    rng = np.random.default_rng(0)
+    p = (p + 0.05 * rng.standard_normal(p.size)).astype(np.float32)  # non-zero biases too
+    q, d2 = widen_params(p, dims, 5, 7, 9, seed=1)
+    assert d2 == (5, 8, 4, 5, 7, 9, -1, 2)
+    s1 = O.Shape(*dims[:6], phi_lo=dims[6], phi_hi=dims[7])
+    s2 = O.Shape(*d2[:6], phi_lo=d2[6], phi_hi=d2[7])
+    assert q.size == s2.nparam
+    x = rng.standard_normal((2, dims[0], dims[1], 8))
+    y1, _ = O.forward(s1, p.astype(np.float64), x, bf16=False)
+    y2, _ = O.forward(s2, q.astype(np.float64), x, bf16=False)
+    assert np.allclose(y1, y2, rtol=0, atol=1e-12)
+    # old weights are carried over in place
+    o1, o2 = s1.unpack(p), s2.unpack(q)
+    assert np.array_equal(o2[0][:, :3], o1[0])
+    assert np.array_equal(o2[2].reshape(9, 5, 7)[:, :3, :4], o1[2].reshape(9, 3, 4))
+    assert np.array_equal(o2[6][:6], o1[6]) and not o2[6][6:].any()
+    # every block of new weights receives a gradient
+    t = rng.standard_normal(y2.shape)
+    _, g = O.loss_grad(s2, q.astype(np.float64), x, t, bf16=False)
+    G = s2.unpack(g)
+    assert np.abs(G[6][6:]).max() > 0          # new decoder rows (outgoing)
+    assert np.abs(G[4][4:]).max() > 0          # new second-layer channels (outgoing)
+    assert np.abs(G[2].reshape(9, 5, 7)[:, 3:, :]).max() > 0  # new first-layer channels
+
+
+def test_plain_cache_round_trip(tmp_path):
+    from paper_2501_15923_amd.synth import Grid
+    from paper_2501_15923_amd.warmstart import PlainCache
+    g = Grid(12, 4, 6)
+    path = str(tmp_path / "plain.npz")
+    c = PlainCache(path, g, 1.5e6)
+    assert c.get(7) is None
+    ref = np.arange(48.0).reshape(2, 4, 6)
+    c.put(7, dict(ref=ref, steps=350, wall=1.25, converged=True,
+                  history=[(50, 0.1, 1e-3, 0.5, 0.2)]))
+    c2 = PlainCache(path, g, 1.5e6)
+    got = c2.get(7)
+    assert got["steps"] == 350 and got["converged"] and np.array_equal(got["ref"], ref)
+    assert got["history"][0][0] == 50
+    assert PlainCache(path, g, 2.0e6).get(7) is None       # another reference time
+    assert PlainCache(path, Grid(12, 4, 8), 1.5e6).get(7) is None  # another grid
