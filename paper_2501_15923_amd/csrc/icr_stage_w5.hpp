@@ -5,11 +5,17 @@
 // A block of 64 x 4 threads marches along phi over a chunk of planes; each
 // row of 64 lanes covers 58 cells plus the three-cell r halo on either side.
 // Per plane the primitives of the tile's rows plus a three-row theta halo
-// sit in LDS; every r and theta face flux is computed once, from six LDS
-// values per variable, and shared by its two cells.  The phi direction is
-// carried in registers: each thread keeps the primitives of planes k-2 ..
-// k+2 of its own column (and loads k+3) and the flux of face k-1/2 from the
-// previous plane.  WENO5 works on primitive variables like the slope
+// sit in LDS; every face flux is computed once and shared by its two cells.
+// In every direction each cell forms both of its WENO5 edge values from its
+// five-cell stencil (the two mirrored reconstructions share the smoothness
+// indicators), and a face pairs the upper value of the cell below with the
+// lower value of the cell above: along r the lane below is one lane down in
+// the same wave (a wave is one row), along theta the row below is another
+// wave and its values pass through LDS, along phi the previous plane's
+// value is carried in registers.  Each thread keeps the primitives of
+// planes k-1 .. k+2 of its own column (and loads k+3), the upper phi edge
+// value of cell k and the flux of face k-1/2 from the previous plane.
+// WENO5 works on primitive variables like the slope
 // limiters (Jiang & Shu 1996 weights, a face state with rho or p <= 0 falls
 // back to its cell value); the weight normalisation multiplies by the
 // Newton-refined reciprocal, as the fluxes do.  Stage 2 also forms the
@@ -23,36 +29,21 @@ namespace icr {
 constexpr int W5_TR = 64, W5_TT = 4, W5_H = 3;
 constexpr int W5_TI = W5_TR - 2 * W5_H;  // cells along r per tile row
 
+// Both edge values of a variable are complete here: without this the
+// compiler forms every variable's upper values first (the shuffle needs
+// them) and keeps the inputs of all lower values live, which spills.  The
+// empty asm emits no instruction.
+template <typename R>
+__device__ __forceinline__ void pin(R& x, R& y) {
+  asm volatile("" : "+v"(x), "+v"(y));
+}
+
 template <typename R>
 struct alignas(16) StageW5 {
   R sW[NV][W5_TT + 2 * W5_H][W5_TR];  // primitives, rows j0-3 .. j0+TT+2
   R sFr[NV][W5_TT][W5_TR];            // r face i-1/2 at the lane of cell i
   R sFt[NV][W5_TT + 1][W5_TR];        // theta face j-1/2 at row j (0 .. TT)
 };
-
-// Face m-1/2 from the six LDS values of cells m-3 .. m+2 (stride apart) of
-// every variable (vstride apart), then the numerical flux.  One variable at
-// a time keeps six values live; the cell-value fallback rereads LDS.
-template <typename R, int N, int FLUX>
-__device__ __forceinline__ void lds_face_w5(const R* base, int stride, int vstride, R gam,
-                                            R igm1, R (&f)[NV]) {
-  R wl[NV], wr[NV];
-#pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    const R* q = base + v * vstride;
-    const R p0 = q[0], p1 = q[stride], p2 = q[2 * stride], p3 = q[3 * stride];
-    const R p4 = q[4 * stride], p5 = q[5 * stride];
-    wl[v] = weno5<R, true>(p0, p1, p2, p3, p4);
-    wr[v] = weno5<R, true>(p5, p4, p3, p2, p1);
-  }
-  if (!(wl[0] > R(0) && wl[4] > R(0)))
-#pragma unroll
-    for (int v = 0; v < NV; ++v) wl[v] = base[v * vstride + 2 * stride];
-  if (!(wr[0] > R(0) && wr[4] > R(0)))
-#pragma unroll
-    for (int v = 0; v < NV; ++v) wr[v] = base[v * vstride + 3 * stride];
-  face_flux<R, N, FLUX, true>(wl, wr, gam, igm1, f);
-}
 
 template <typename R, int FLUX, int STAGE>
 __device__ __forceinline__ void stage_tile_w5(const StageArgs<R>& a, int kplanes, int bx, int by,
@@ -97,25 +88,30 @@ __device__ __forceinline__ void stage_tile_w5(const StageArgs<R>& a, int kplanes
   }
   const R dt = (R)a.clock->dt;
 
-  // phi ring: at the top of iteration k, w0 .. w4 = W(k-2) .. W(k+2) and
-  // fcar = flux of face k-1/2; iteration k0-1 only forms fcar
-  R w0[NV], w1[NV], w2[NV], w3[NV], w4[NV], fcar[NV];
+  // phi ring: at the top of iteration k, w0 .. w3 = W(k-1) .. W(k+2),
+  // ecar = the upper phi edge value of cell k (face k+1/2, left state) and
+  // fcar = flux of face k-1/2; iteration k0-2 only forms ecar, k0-1 only
+  // ecar and fcar
+  R w0[NV], w1[NV], w2[NV], w3[NV], ecar[NV], fcar[NV];
   load_own(k0 - 3, w0);
   load_own(k0 - 2, w1);
   load_own(k0 - 1, w2);
   load_own(k0, w3);
-  load_own(k0 + 1, w4);
 #pragma unroll
-  for (int v = 0; v < NV; ++v) fcar[v] = R(0);
+  for (int v = 0; v < NV; ++v) {
+    fcar[v] = R(0);
+    ecar[v] = R(0);
+  }
 
-  // r face lane: the stencil of lane l reads lanes l-3 .. l+2; halo lanes
-  // take the nearest interior lane's face (never read by the update)
-  const int tf = ti < H ? H : (ti > TR - H ? TR - H : ti);
+  // r edge lane: lane l reads lanes l-2 .. l+2; lanes 2 .. TR-3 give the
+  // edge values of the faces the update reads (lanes H .. TR-H); the outer
+  // two lanes on either side repeat their neighbour's (never read)
+  const int tc = ti < 2 ? 2 : (ti > TR - 3 ? TR - 3 : ti);
 
   double lam = 0.0, s1 = 0.0, s0 = 0.0;
   int bad = BAD_NONE;
 
-  for (int k = k0 - 1; k < kend; ++k) {
+  for (int k = k0 - 2; k < kend; ++k) {
     const bool body = k >= k0;  // uniform over the block
     const unsigned kbase = (unsigned)k * plane_cells;
     if (body) {
@@ -125,17 +121,17 @@ __device__ __forceinline__ void stage_tile_w5(const StageArgs<R>& a, int kplanes
 #pragma unroll
         for (int v = 0; v < NV; ++v) w[v] = ldg(a.ghost + v * gplane, (unsigned)(k * nt + mj));
         if (flipj) flip_theta(w);
-        if (a.asymm) {  // w2: the mirror cell's primitives (already flipped)
-          w[2] = -w2[2];
-          w[3] = -w2[3];
-          w[6] = -w2[6];
-          w[7] = -w2[7];
+        if (a.asymm) {  // w1: the mirror cell's primitives (already flipped)
+          w[2] = -w1[2];
+          w[3] = -w1[3];
+          w[6] = -w1[6];
+          w[7] = -w1[7];
         }
 #pragma unroll
         for (int v = 0; v < NV; ++v) sW[v][tj + H][ti] = w[v];
       } else {
 #pragma unroll
-        for (int v = 0; v < NV; ++v) sW[v][tj + H][ti] = w2[v];
+        for (int v = 0; v < NV; ++v) sW[v][tj + H][ti] = w1[v];
       }
       // theta halo: rows -3 .. -1 and TT .. TT+2 over all TR lanes
       for (int h = tid; h < 2 * H * TR; h += NT) {
@@ -159,25 +155,88 @@ __device__ __forceinline__ void stage_tile_w5(const StageArgs<R>& a, int kplanes
       __syncthreads();
       constexpr int VS = WT * TR;
       {
-        R f[NV];
-        lds_face_w5<R, 1, FLUX>(&sW[0][tj + H][tf] - H, 1, VS, a.gam, a.igm1, f);
+        // both r edge values of the lane's cell from lanes tc-2 .. tc+2; the
+        // face i-1/2 takes the upper value of lane ti-1 (one lane up in the
+        // wave, the row being one wave) and the lower value of lane ti
+        R eu[NV], ed[NV], f[NV];
+        const R* q = &sW[0][tj + H][tc];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          weno5_cell<R, true>(q[v * VS - 2], q[v * VS - 1], q[v * VS], q[v * VS + 1],
+                              q[v * VS + 2], eu[v], ed[v]);
+          pin(eu[v], ed[v]);
+        }
+        if (!(eu[0] > R(0) && eu[4] > R(0)))
+#pragma unroll
+          for (int v = 0; v < NV; ++v) eu[v] = q[v * VS];
+        if (!(ed[0] > R(0) && ed[4] > R(0)))
+#pragma unroll
+          for (int v = 0; v < NV; ++v) ed[v] = q[v * VS];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) eu[v] = __shfl_up(eu[v], 1, 64);
+        face_flux<R, 1, FLUX, true>(eu, ed, a.gam, a.igm1, f);
 #pragma unroll
         for (int v = 0; v < NV; ++v) sFr[v][tj][ti] = f[v];
       }
+      // theta: both edge values of the lane's cell from sW rows tj+1 ..
+      // tj+5; wave 0 also forms the upper value of the row below the tile
+      // (cell j0-1) and wave TT-1 the lower value of the row above it (cell
+      // j0+TT), with the same expressions as the neighbouring tiles, so a
+      // face shared by two tiles gets the same flux in both
+      R tu[NV], td[NV], xe[NV];
       {
+        const R* q = &sW[0][tj + H][ti];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          weno5_cell<R, true>(q[v * VS - 2 * TR], q[v * VS - TR], q[v * VS], q[v * VS + TR],
+                              q[v * VS + 2 * TR], tu[v], td[v]);
+          pin(tu[v], td[v]);
+        }
+        if (!(tu[0] > R(0) && tu[4] > R(0)))
+#pragma unroll
+          for (int v = 0; v < NV; ++v) tu[v] = q[v * VS];
+        if (!(td[0] > R(0) && td[4] > R(0)))
+#pragma unroll
+          for (int v = 0; v < NV; ++v) td[v] = q[v * VS];
+      }
+      const bool lo_wave = tj == 0, hi_wave = tj == TT - 1;  // uniform per wave
+      if (lo_wave || hi_wave) {
+        const R* q = &sW[0][lo_wave ? H - 1 : TT + H][ti];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) {
+          R eu, ed;
+          weno5_cell<R, true>(q[v * VS - 2 * TR], q[v * VS - TR], q[v * VS], q[v * VS + TR],
+                              q[v * VS + 2 * TR], eu, ed);
+          xe[v] = lo_wave ? eu : ed;
+        }
+        if (!(xe[0] > R(0) && xe[4] > R(0)))
+#pragma unroll
+          for (int v = 0; v < NV; ++v) xe[v] = q[v * VS];
+      }
+      // the left states of the faces at rows 0 .. TT-1 go through the flux
+      // rows (row tj is then read and overwritten by wave tj alone): the
+      // upper values of rows 0 .. TT-2 and of the row below the tile; wave
+      // TT-1 finishes the tile's upper face (row TT) from its own values
+      if (!hi_wave)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sFt[v][tj + 1][ti] = tu[v];
+      if (lo_wave)
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sFt[v][0][ti] = xe[v];
+      if (hi_wave) {
         R f[NV];
-        lds_face_w5<R, 2, FLUX>(&sW[0][tj][ti], TR, VS, a.gam, a.igm1, f);
+        face_flux<R, 2, FLUX, true>(tu, xe, a.gam, a.igm1, f);
+#pragma unroll
+        for (int v = 0; v < NV; ++v) sFt[v][TT][ti] = f[v];
+      }
+      __syncthreads();
+      {
+        R lft[NV], f[NV];
+#pragma unroll
+        for (int v = 0; v < NV; ++v) lft[v] = sFt[v][tj][ti];
+        face_flux<R, 2, FLUX, true>(lft, td, a.gam, a.igm1, f);
 #pragma unroll
         for (int v = 0; v < NV; ++v) sFt[v][tj][ti] = f[v];
-      }
-      // the tile's upper theta face (row TT) of the inner lanes: wave 1
-      for (int q = tid - 64; q >= 0 && q < TR; q += NT - 64) {
-        if (q >= H && q < TR - H) {
-          R f[NV];
-          lds_face_w5<R, 2, FLUX>(&sW[0][TT][q], TR, VS, a.gam, a.igm1, f);
-#pragma unroll
-          for (int v = 0; v < NV; ++v) sFt[v][TT][q] = f[v];
-        }
       }
     }
     // stage 2: the own cell's U^n for the RK combine, issued early
@@ -187,23 +246,38 @@ __device__ __forceinline__ void stage_tile_w5(const StageArgs<R>& a, int kplanes
 #pragma unroll
       for (int v = 0; v < NV; ++v) up[v] = ldg(a.un + v * a.ncell, c);
     }
-    // phi face k+1/2 from W(k-2) .. W(k+3)
+    // phi edge values of cell k+1 from W(k-1) .. W(k+3); face k+1/2 from
+    // the carried upper value of cell k and the lower value of cell k+1
     R fhi[NV];
     {
-      R w5[NV], wl[NV], wr[NV];
-      load_own(k + 3, w5);
-      reconstruct_weno5<R, true>(w0, w1, w2, w3, w4, w5, wl, wr);
-      face_flux<R, 3, FLUX, true>(wl, wr, a.gam, a.igm1, fhi);
+      R w4[NV], eu[NV], ed[NV];
+      load_own(k + 3, w4);
 #pragma unroll
       for (int v = 0; v < NV; ++v) {
+        weno5_cell<R, true>(w0[v], w1[v], w2[v], w3[v], w4[v], eu[v], ed[v]);
+        pin(eu[v], ed[v]);
+      }
+      if (!(eu[0] > R(0) && eu[4] > R(0)))
+#pragma unroll
+        for (int v = 0; v < NV; ++v) eu[v] = w2[v];
+      if (!(ed[0] > R(0) && ed[4] > R(0)))
+#pragma unroll
+        for (int v = 0; v < NV; ++v) ed[v] = w2[v];
+      if (k >= k0 - 1)
+        face_flux<R, 3, FLUX, true>(ecar, ed, a.gam, a.igm1, fhi);
+      else
+#pragma unroll
+        for (int v = 0; v < NV; ++v) fhi[v] = R(0);
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        ecar[v] = eu[v];
         w0[v] = w1[v];
         w1[v] = w2[v];
         w2[v] = w3[v];
         w3[v] = w4[v];
-        w4[v] = w5[v];
       }
     }
-    // now w1 = W(k), w2 = W(k+1)
+    // now w0 = W(k), w1 = W(k+1)
     if (body) {
       __syncthreads();  // r / theta face fluxes are in LDS
       if (valid) {
@@ -219,9 +293,9 @@ __device__ __forceinline__ void stage_tile_w5(const StageArgs<R>& a, int kplanes
           L[v] -= hr * (sp * sFt[v][tj + 1][ti] - sm * sFt[v][tj][ti]) * ict;
           L[v] -= fph * (fhi[v] - fcar[v]);
         }
-        add_sources<R>(w1, a.m, ic, jc, a.omega, a.gravity, a.corot, L);
+        add_sources<R>(w0, a.m, ic, jc, a.omega, a.gravity, a.corot, L);
         R uc[NV];
-        prim2cons<R>(w1, uc, a.igm1);
+        prim2cons<R>(w0, uc, a.igm1);
         const unsigned c = kbase + colbase;
         if (STAGE == 1) {
 #pragma unroll
