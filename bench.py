@@ -440,7 +440,7 @@ def copy_calibration():
     print(json.dumps({"copy_bytes": 8 * n, "launches": 3}), flush=True)
 
 
-def ingest_counters(dirs, precision, out_path):
+def ingest_counters(dirs, precision, out_path, launch=None):
     """Turn four rocprofv3 --pmc runs (FETCH_SIZE and WRITE_SIZE of this
     bench, then of --copy-calibration) into HBM bytes per stage-2 launch.
     Each counter is scaled by what it reads for the 2 GiB copy.  A fifth run
@@ -479,7 +479,9 @@ def ingest_counters(dirs, precision, out_path):
     rec = {"precision": precision, "kernel_rev": kernel_rev(),
            "fetch_bytes": fetch * sf, "write_bytes": write * sw,
            "bytes_per_launch": fetch * sf + write * sw,
-           "fetch_scale": sf, "write_scale": sw, "dispatches": [n_f, n_w]}
+           "fetch_scale": sf, "write_scale": sw, "dispatches": [n_f, n_w],
+           "flux": "tvdlf", "limiter": "minmod",
+           "launch": [int(v) for v in launch.split(",")] if launch else None}
     if len(dirs) == 5:
         rec["valu_wave_instr_per_launch"], _ = stage2_mean(dirs[4], "SQ_INSTS_VALU")
     json.dump(rec, open(out_path, "w"), indent=1)
@@ -541,7 +543,7 @@ def main():
         copy_calibration()
         return
     if args.ingest_counters:
-        ingest_counters(args.ingest_counters, args.precision, args.traffic)
+        ingest_counters(args.ingest_counters, args.precision, args.traffic, args.launch)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (got --gpus {args.gpus}); the multi-GPU "
@@ -619,7 +621,12 @@ def main():
     if os.path.exists(args.traffic):
         try:
             tr = json.load(open(args.traffic))
-            if tr.get("precision") == args.precision and tr.get("kernel_rev") == kernel_rev():
+            # the record holds for the kernel, scheme and launch shape it was taken on
+            same = (tr.get("precision") == args.precision and tr.get("kernel_rev") == kernel_rev()
+                    and tr.get("flux", "tvdlf") == args.flux
+                    and tr.get("limiter", "minmod") == args.limiter
+                    and tr.get("launch") in (None, [tile_r or 64, planes or 8]))
+            if same:
                 traffic = tr.get("bytes_per_launch")
                 vi = tr.get("valu_wave_instr_per_launch")
                 if vi:

@@ -60,9 +60,14 @@ def _time(fn, reps):
 
 def solver_candidates(g, limiter=0):
     out = []
-    # the WENO5 face-once tile exists in the 64-lane shape only
+    # the WENO5 face-once tile exists in the 64-lane shape only; its 58-cell
+    # rows make 11 tiles along r at n_r = 600, so chunks of 20-40 planes give
+    # grids of about one or two rounds of the resident blocks
+    plist = (2, 4, 5, 6, 8, 10, 12, 15, 16)
+    if limiter == 2:
+        plist += (20, 24, 30, 40)
     for tr in ((64,) if limiter == 2 else (64, 32)):
-        for planes in (2, 4, 5, 6, 8, 10, 12, 15, 16):
+        for planes in plist:
             if planes <= g.np_:
                 out.append((tr, planes))
     return out
