@@ -102,26 +102,35 @@ def ensemble_bench(args):
     log(f"bench: ensemble of {len(grids)} runs, {cells / 1e6:.1f} M cells, fp{args.precision}")
     persistent, planes = autotune.tune_ensemble(grids, precision=args.precision)
     log(f"bench: autotuner chose persistent={persistent}, planes {sorted(set(planes))}")
-    e = Ensemble(grids, precision=args.precision)
-    for m, run in zip(members, e.runs):
-        run.set_maps(m["times"], m["maps"])
-        run.set_cmes(m["cme"][None])
-        run.init_radial()
-    for r, p in enumerate(planes):
-        e.set_planes(r, p)
-    e.set_mode(persistent, 0, 1)
-    e.step(args.warmup)
-    torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
-    ev0.record()
-    info = e.step(args.steps)
-    ev1.record()
-    torch.cuda.synchronize()
-    ms = ev0.elapsed_time(ev1)
-    assert all(i["steps"] == args.steps and i["status"] == 0 for i in info)
-    e.close()
-    del e
+
+    def timed(mode):
+        """The ensemble from its initial state in one mode: warm-up, then K
+        timed steps (each mode steps the same runs over the same times)."""
+        e = Ensemble(grids, precision=args.precision)
+        for m, run in zip(members, e.runs):
+            run.set_maps(m["times"], m["maps"])
+            run.set_cmes(m["cme"][None])
+            run.init_radial()
+        for r, p in enumerate(planes):
+            e.set_planes(r, p)
+        e.set_mode(mode, 0, 1)
+        e.step(args.warmup)
+        torch.cuda.synchronize()
+        ev0.record()
+        info = e.step(args.steps)
+        ev1.record()
+        torch.cuda.synchronize()
+        assert all(i["steps"] == args.steps and i["status"] == 0 for i in info)
+        e.close()
+        return ev0.elapsed_time(ev1)
+    ms = timed(persistent)
+    torch.cuda.empty_cache()
+    # the other mode, for the record (same planes, hipGraph)
+    ms_other = timed(1 - persistent)
+    log(f"bench: {'batched' if persistent else 'persistent'} mode {args.steps} steps in "
+        f"{ms_other:.1f} ms")
     torch.cuda.empty_cache()
     value = cells * args.steps / (ms * 1e-3)
     log(f"bench: ensemble {args.steps} steps in {ms:.1f} ms")
@@ -153,6 +162,9 @@ def ensemble_bench(args):
         "sequential": {"value": seq, "unit": "cell-updates/s",
                        "ms_per_step": seq_ms / args.steps},
         "speedup_vs_sequential": value / seq,
+        "modes": {name: {"ms_per_step": t / args.steps, "value": cells * args.steps / (t * 1e-3)}
+                  for name, t in ((("persistent", ms), ("batched", ms_other)) if persistent
+                                  else (("persistent", ms_other), ("batched", ms)))},
     }
     print(json.dumps(out), flush=True)
 
@@ -484,8 +496,19 @@ def ingest_counters(dirs, precision, out_path, launch=None):
            "launch": [int(v) for v in launch.split(",")] if launch else None}
     if len(dirs) == 5:
         rec["valu_wave_instr_per_launch"], _ = stage2_mean(dirs[4], "SQ_INSTS_VALU")
-    json.dump(rec, open(out_path, "w"), indent=1)
+    # one record per (precision, launch shape): replace that one, keep the others
+    recs = [r for r in traffic_records(out_path)
+            if (r.get("precision"), r.get("launch")) != (rec["precision"], rec["launch"])]
+    json.dump({"records": recs + [rec]}, open(out_path, "w"), indent=1)
     print(json.dumps(rec), flush=True)
+
+
+def traffic_records(path):
+    """The counter records of a traffic file (a single record or {"records": [...]})."""
+    if not os.path.exists(path):
+        return []
+    d = json.load(open(path))
+    return d["records"] if "records" in d else [d]
 
 
 def _cpu_model():
@@ -620,13 +643,15 @@ def main():
     valu = None
     if os.path.exists(args.traffic):
         try:
-            tr = json.load(open(args.traffic))
-            # the record holds for the kernel, scheme and launch shape it was taken on
-            same = (tr.get("precision") == args.precision and tr.get("kernel_rev") == kernel_rev()
-                    and tr.get("flux", "tvdlf") == args.flux
-                    and tr.get("limiter", "minmod") == args.limiter
-                    and tr.get("launch") in (None, [tile_r or 64, planes or 8]))
-            if same:
+            # a record holds for the kernel, scheme and launch shape it was taken on
+            match = [tr for tr in traffic_records(args.traffic)
+                     if tr.get("precision") == args.precision
+                     and tr.get("kernel_rev") == kernel_rev()
+                     and tr.get("flux", "tvdlf") == args.flux
+                     and tr.get("limiter", "minmod") == args.limiter
+                     and tr.get("launch") in (None, [tile_r or 64, planes or 8])]
+            if match:
+                tr = match[-1]
                 traffic = tr.get("bytes_per_launch")
                 vi = tr.get("valu_wave_instr_per_launch")
                 if vi:

@@ -29,6 +29,58 @@ namespace icr {
 constexpr int W5_TR = 64, W5_TT = 4, W5_H = 3;
 constexpr int W5_TI = W5_TR - 2 * W5_H;  // cells along r per tile row
 
+// Both WENO5 edge values of the cell c from the five cells a..e: up = the
+// value at the face between c and d (weno5(a, b, c, d, e)), dn = the value
+// at the face between b and c (weno5(e, d, c, b, a)).  The mirrored stencil
+// has the same three smoothness indicators in reverse order and the same
+// eps, so they are formed once; the expressions are symmetric under
+// a..e -> e..a, so a mirror-symmetric flow keeps mirror-symmetric states.
+// Equal to the two weno5 calls up to rounding.
+template <typename R, bool FAST = false>
+__device__ __forceinline__ void weno5_cell(R a, R b, R c, R d, R e, R& up, R& dn) {
+  const R s0 = (a + c) - R(2) * b, t0 = (a - R(4) * b) + R(3) * c;
+  const R s1 = (b + d) - R(2) * c, t1 = b - d;
+  const R s2 = (e + c) - R(2) * d, t2 = (e - R(4) * d) + R(3) * c;
+  const R b0 = R(13) / R(12) * s0 * s0 + R(0.25) * t0 * t0;
+  const R b1 = R(13) / R(12) * s1 * s1 + R(0.25) * t1 * t1;
+  const R b2 = R(13) / R(12) * s2 * s2 + R(0.25) * t2 * t2;
+  const R eps = R(1e-6) * ((a * a + e * e) + (b * b + d * d) + c * c) * R(0.2) +
+                (sizeof(R) == 8 ? R(1e-40) : R(1e-15));
+  const R g0 = (eps + b0) * (eps + b0), g1 = (eps + b1) * (eps + b1), g2 = (eps + b2) * (eps + b2);
+  // candidates times 6: up uses the stencils ending at / centred on /
+  // starting at c read from a, dn the same read from e
+  const R u0 = (R(2) * a - R(7) * b) + R(11) * c, u1 = (R(5) * c - b) + R(2) * d;
+  const R u2 = (R(2) * c - e) + R(5) * d;
+  const R d0 = (R(2) * e - R(7) * d) + R(11) * c, d1 = (R(5) * c - d) + R(2) * b;
+  const R d2 = (R(2) * c - a) + R(5) * b;
+  constexpr R sixth = R(1) / R(6);
+  if constexpr (sizeof(R) == 8) {
+    // weights d_k / g_k scaled by g0 g1 g2 (one reciprocal per value)
+    const R p12 = g1 * g2, p02 = g0 * g2, p01 = g0 * g1;
+    const R ua0 = R(0.1) * p12, ua1 = R(0.6) * p02, ua2 = R(0.3) * p01;
+    const R da0 = R(0.1) * p01, da2 = R(0.3) * p12;
+    const R un = ua0 * u0 + ua1 * u1 + ua2 * u2, us = ua0 + ua1 + ua2;
+    const R dnn = da0 * d0 + ua1 * d1 + da2 * d2, ds = da0 + ua1 + da2;
+    if constexpr (FAST) {
+      up = un * rcp_fast(us) * sixth;
+      dn = dnn * rcp_fast(ds) * sixth;
+    } else {
+      up = un / us * sixth;
+      dn = dnn / ds * sixth;
+    }
+  } else {
+    const R i0 = FAST ? rcp_fast(g0) : R(1) / g0;
+    const R i1 = FAST ? rcp_fast(g1) : R(1) / g1;
+    const R i2 = FAST ? rcp_fast(g2) : R(1) / g2;
+    const R ua0 = R(0.1) * i0, ua1 = R(0.6) * i1, ua2 = R(0.3) * i2;
+    const R da0 = R(0.1) * i2, da2 = R(0.3) * i0;
+    const R un = ua0 * u0 + ua1 * u1 + ua2 * u2, us = ua0 + ua1 + ua2;
+    const R dnn = da0 * d0 + ua1 * d1 + da2 * d2, ds = da0 + ua1 + da2;
+    up = un / us * sixth;
+    dn = dnn / ds * sixth;
+  }
+}
+
 // Both edge values of a variable are complete here: without this the
 // compiler forms every variable's upper values first (the shuffle needs
 // them) and keeps the inputs of all lower values live, which spills.  The

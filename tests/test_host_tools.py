@@ -61,13 +61,22 @@ def test_ingest_counters_scales_by_the_copy_and_adds_valu(tmp_path):
     _write_counters(d[4], [dict(Kernel_Name=k2, Counter_Name="SQ_INSTS_VALU", Counter_Value=64.0),
                            dict(Kernel_Name=k2, Counter_Name="SQ_WAVES", Counter_Value=1.0)])
     out = str(tmp_path / "t.json")
-    bench.ingest_counters(d[:4], 64, out)
-    rec = json.load(open(out))
+    bench.ingest_counters(d[:4], 64, out, "64,12")
+    (rec,) = bench.traffic_records(out)
     assert rec["fetch_bytes"] == 1100.0 * 2048 and rec["write_bytes"] == 500.0 * 1024
     assert rec["bytes_per_launch"] == rec["fetch_bytes"] + rec["write_bytes"]
     assert rec["kernel_rev"] == bench.kernel_rev() and "valu_wave_instr_per_launch" not in rec
-    bench.ingest_counters(d, 64, out)
-    assert json.load(open(out))["valu_wave_instr_per_launch"] == 64.0
+    assert rec["launch"] == [64, 12] and rec["flux"] == "tvdlf" and rec["limiter"] == "minmod"
+    # the same launch shape again replaces its record; another one is kept beside it
+    bench.ingest_counters(d, 64, out, "64,12")
+    (rec,) = bench.traffic_records(out)
+    assert rec["valu_wave_instr_per_launch"] == 64.0
+    bench.ingest_counters(d[:4], 64, out, "64,15")
+    recs = bench.traffic_records(out)
+    assert [r["launch"] for r in recs] == [[64, 12], [64, 15]]
+    # a file holding one bare record still reads
+    json.dump(rec, open(out, "w"))
+    assert bench.traffic_records(out) == [rec]
 
 
 def test_relaxation_criteria_pick_the_first_record_meeting_both():
