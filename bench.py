@@ -100,7 +100,10 @@ def ensemble_bench(args):
     grids = [m["grid"] for m in members]
     cells = sum(g.cells for g in grids)
     log(f"bench: ensemble of {len(grids)} runs, {cells / 1e6:.1f} M cells, fp{args.precision}")
-    persistent, planes = autotune.tune_ensemble(grids, precision=args.precision)
+    flux = {"tvdlf": 0, "hll": 1, "hlld": 2}[args.flux]
+    lim = {"minmod": 0, "mc": 1, "weno5": 2}[args.limiter]
+    scheme = dict(flux=flux, limiter=lim)
+    persistent, planes = autotune.tune_ensemble(grids, precision=args.precision, **scheme)
     log(f"bench: autotuner chose persistent={persistent}, planes {sorted(set(planes))}")
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
@@ -108,7 +111,7 @@ def ensemble_bench(args):
     def timed(mode):
         """The ensemble from its initial state in one mode: warm-up, then K
         timed steps (each mode steps the same runs over the same times)."""
-        e = Ensemble(grids, precision=args.precision)
+        e = Ensemble(grids, precision=args.precision, **scheme)
         for m, run in zip(members, e.runs):
             run.set_maps(m["times"], m["maps"])
             run.set_cmes(m["cme"][None])
@@ -136,11 +139,11 @@ def ensemble_bench(args):
     log(f"bench: ensemble {args.steps} steps in {ms:.1f} ms")
     seq_ms = 0.0
     for m in members:
-        s = Solver(m["grid"], precision=args.precision)
+        s = Solver(m["grid"], precision=args.precision, **scheme)
         s.set_maps(m["times"], m["maps"])
         s.set_cmes(m["cme"][None])
         s.init_radial()
-        s.set_launch(2, *autotune.tune_solver(m["grid"], precision=args.precision), 1)
+        s.set_launch(2, *autotune.tune_solver(m["grid"], precision=args.precision, **scheme), 1)
         s.step(args.warmup)
         torch.cuda.synchronize()
         ev0.record()
@@ -158,6 +161,7 @@ def ensemble_bench(args):
         "vs_baseline": None, "dtype": f"f{args.precision}", "data": "synthetic",
         "config": {"workload": (f"ensemble_{len(grids)}_runs_{args.ens_grid}" if fixed else
                                 f"ensemble_{len(grids)}_uneven_runs"), "cells": cells,
+                   "flux": args.flux.upper(), "limiter": args.limiter,
                    "persistent": int(persistent), "planes": sorted(set(planes))},
         "sequential": {"value": seq, "unit": "cell-updates/s",
                        "ms_per_step": seq_ms / args.steps},

@@ -308,7 +308,8 @@ int icr_boundary_at(icr_solver *s, double t_s, double *out);
  * tile_r: lanes along r per block (variant 1: 64, 128, 256; variant 2: 32,
  * 64, of which the first two and the last two hold the r halo, so a block
  * updates tile_r - 4 cells along r; 0 = 64; a solver with the passive
- * tracer keeps 64 for variant 2; a WENO5 solver always runs variant 1);
+ * tracer keeps 64 for variant 2; a WENO5 solver's variant 2 is its own
+ * 64-lane tile of 58 cells along r, and with the tracer it runs variant 1);
  * 256 threads per block.  planes: phi planes per block of
  * variant 2 (1..n_phi, 0 = 8).  use_graphs: 1 replays steps from captured
  * HIP graphs.  All tiles and plane counts of one variant give bit-identical
@@ -346,8 +347,9 @@ int icr_fast_math(const double *x, long long n, double *rcp, double *sq, void *h
 typedef struct icr_ensemble icr_ensemble;
 
 /* Device bytes for n_runs grids (grids[n_runs]) sharing one icr_phys.
- * Every flux and the tracer are supported; WENO5 is not
- * (ICR_ERR_UNSUPPORTED). */
+ * Every flux, limiter and the tracer are supported, except WENO5 together
+ * with the tracer (ICR_ERR_UNSUPPORTED): the WENO5 tile keeps no face mass
+ * fluxes. */
 int icr_ens_workspace_bytes(int n_runs, const icr_grid *grids,
                             const icr_phys *phys, size_t *bytes);
 

@@ -1266,7 +1266,9 @@ RunDesc<R> make_desc(icr_solver* s, int planes) {
   d.tghost1 = (R*)s->tg(1);
   d.clock = s->clock();
   d.partials = (double*)(s->ws + s->L.partials);
-  d.nbx = (s->g.n_r + tile_cells_r(64) - 1) / tile_cells_r(64);
+  // the tile grid of the run's stage kernel (WENO5: 58 cells along r)
+  const int ti = s->p.limiter == ICR_LIM_WENO5 ? W5_TI : tile_cells_r(64);
+  d.nbx = (s->g.n_r + ti - 1) / ti;
   d.nby = (s->g.n_theta + 3) / 4;
   d.nbz = (s->g.n_phi + planes - 1) / planes;
   d.planes = planes;
@@ -1340,8 +1342,9 @@ extern "C" {
 
 int icr_ens_workspace_bytes(int n, const icr_grid* grids, const icr_phys* phys, size_t* bytes) {
   if (n < 1 || !grids || !bytes) return fail(ICR_ERR_ARG, "need n >= 1, grids and bytes");
-  if (phys && phys->limiter == ICR_LIM_WENO5)
-    return fail(ICR_ERR_UNSUPPORTED, "WENO5 is available for single solvers only");
+  if (phys && phys->limiter == ICR_LIM_WENO5 && phys->tracer)
+    return fail(ICR_ERR_UNSUPPORTED,
+                "WENO5 with the passive tracer is available for single solvers only");
   size_t total = ens_table_bytes(n);
   for (int r = 0; r < n; ++r) {
     int rc = validate(&grids[r], phys);

@@ -111,6 +111,19 @@ __device__ __forceinline__ void stage_item(const RunDesc<R>* runs, const EnsTabl
                                              by, bz, local, smw, smf);
 }
 
+// WENO5: the 64 x 4 face-once tile with the three-cell halo (no tracer)
+template <typename R, int FLUX, int STAGE>
+__device__ __forceinline__ void stage_item_w5(const RunDesc<R>* runs, const EnsTables& e,
+                                              int item, int step, StageW5<R>& sm) {
+  const int r = find_run(e.tile_off, e.n_runs, item);
+  const RunDesc<R>& rd = runs[r];
+  const int local = item - e.tile_off[r];
+  const int par = (rd.par + step) & 1;
+  const int bx = local % rd.nbx, by = (local / rd.nbx) % rd.nby, bz = local / (rd.nbx * rd.nby);
+  stage_tile_w5<R, FLUX, STAGE>(STAGE == 1 ? rd.s1[par] : rd.s2[par], rd.planes, bx, by, bz,
+                                local, sm);
+}
+
 template <typename R>
 __device__ __forceinline__ void fin_item(const RunDesc<R>* runs, int r) {
   const RunDesc<R>& rd = runs[r];
@@ -147,6 +160,23 @@ k_ensemble(const RunDesc<R>* __restrict__ runs, EnsTables e, int nsteps) {
   }
 }
 
+template <typename R, int FLUX>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_ensemble_w5(const RunDesc<R>* __restrict__ runs, EnsTables e, int nsteps) {
+  const unsigned G = gridDim.x;
+  __shared__ StageW5<R> sm;
+  for (int s = 0; s < nsteps; ++s) {
+    for_items(e.n_bitems, [&](int it) { bnd_item<R>(runs, e, it); });
+    if (!grid_sync(e.bar, G, e.spin_limit)) return;
+    for_items(e.n_tiles, [&](int it) { stage_item_w5<R, FLUX, 1>(runs, e, it, s, sm); });
+    if (!grid_sync(e.bar, G, e.spin_limit)) return;
+    for_items(e.n_tiles, [&](int it) { stage_item_w5<R, FLUX, 2>(runs, e, it, s, sm); });
+    if (!grid_sync(e.bar, G, e.spin_limit)) return;
+    for_items(e.n_runs, [&](int r) { fin_item<R>(runs, r); });
+    if (!grid_sync(e.bar, G, e.spin_limit)) return;
+  }
+}
+
 // ---- batched mode: one launch per work list (grid = items) ---------------
 template <typename R>
 __global__ void __launch_bounds__(256) k_ens_bnd(const RunDesc<R>* __restrict__ runs, EnsTables e) {
@@ -159,6 +189,12 @@ k_ens_stage(const RunDesc<R>* __restrict__ runs, EnsTables e, int step) {
   __shared__ StageF<R, 64, 4> smf;
   for_items(e.n_tiles,
             [&](int it) { stage_item<R, FLUX, LIM, STAGE, FM>(runs, e, it, step, smw, smf); });
+}
+template <typename R, int FLUX, int STAGE>
+__global__ void __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2)))
+k_ens_stage_w5(const RunDesc<R>* __restrict__ runs, EnsTables e, int step) {
+  __shared__ StageW5<R> sm;
+  for_items(e.n_tiles, [&](int it) { stage_item_w5<R, FLUX, STAGE>(runs, e, it, step, sm); });
 }
 template <typename R, int STAGE>
 __global__ void __launch_bounds__(256) k_ens_trc(const RunDesc<R>* __restrict__ runs, EnsTables e,
@@ -208,6 +244,23 @@ static void ens_launch(const EnsLaunch& L, hipStream_t s) {
   }
 }
 
+template <typename R, int FLUX>
+static void ens_launch_w5(const EnsLaunch& L, hipStream_t s) {
+  const RunDesc<R>* runs = (const RunDesc<R>*)L.runs;
+  const dim3 blk(64, 4);
+  if (L.persistent) {
+    hipLaunchKernelGGL((k_ensemble_w5<R, FLUX>), dim3(L.grid), blk, 0, s, runs, L.e, L.nsteps);
+    return;
+  }
+  auto items = [](int n) { return dim3((unsigned)((n + NXCD - 1) / NXCD * NXCD)); };
+  for (int q = 0; q < L.nsteps; ++q) {
+    hipLaunchKernelGGL(k_ens_bnd<R>, items(L.e.n_bitems), blk, 0, s, runs, L.e);
+    hipLaunchKernelGGL((k_ens_stage_w5<R, FLUX, 1>), items(L.e.n_tiles), blk, 0, s, runs, L.e, q);
+    hipLaunchKernelGGL((k_ens_stage_w5<R, FLUX, 2>), items(L.e.n_tiles), blk, 0, s, runs, L.e, q);
+    hipLaunchKernelGGL(k_ens_fin<R>, items(L.e.n_runs), blk, 0, s, runs, L.e);
+  }
+}
+
 template <typename R, int FLUX, int LIM>
 static void ens_launch_fm(const EnsLaunch& L, hipStream_t s) {
   if (L.tracer) ens_launch<R, FLUX, LIM, true>(L, s);
@@ -217,6 +270,7 @@ static void ens_launch_fm(const EnsLaunch& L, hipStream_t s) {
 template <typename R, int FLUX>
 static void ens_launch_lim(const EnsLaunch& L, hipStream_t s) {
   if (L.lim == LIM_MINMOD) ens_launch_fm<R, FLUX, LIM_MINMOD>(L, s);
+  else if (L.lim == LIM_WENO5) ens_launch_w5<R, FLUX>(L, s);  // the host rejects the tracer
   else ens_launch_fm<R, FLUX, LIM_MC>(L, s);
 }
 
@@ -248,6 +302,11 @@ static const void* ens_fn(bool tracer) {
 
 template <typename R>
 static const void* ens_fn_r(int flux, int lim, bool tracer) {
+  if (lim == LIM_WENO5) {
+    if (flux == FLUX_TVDLF) return reinterpret_cast<const void*>(&k_ensemble_w5<R, FLUX_TVDLF>);
+    if (flux == FLUX_HLLD) return reinterpret_cast<const void*>(&k_ensemble_w5<R, FLUX_HLLD>);
+    return reinterpret_cast<const void*>(&k_ensemble_w5<R, FLUX_HLL>);
+  }
   const bool mm = lim == LIM_MINMOD;
   if (flux == FLUX_TVDLF)
     return mm ? ens_fn<R, FLUX_TVDLF, LIM_MINMOD>(tracer) : ens_fn<R, FLUX_TVDLF, LIM_MC>(tracer);

@@ -1,6 +1,7 @@
 // icr_ensemble.hpp -- device tables of the batched ensemble.
 #pragma once
 #include "icr_stage_lds.hpp"
+#include "icr_stage_w5.hpp"
 
 namespace icr {
 

@@ -1,8 +1,8 @@
 """Batched ensemble on the GPU: every run is bit-identical to the same run
 stepped alone through icr_step, in the persistent (one launch, device-wide
 barriers) and the batched (one launch per phase) modes, also with the HLLD
-flux and with the passive CME tracer (state and tracer bitwise), and one run
-is checked against the oracle."""
+flux, with the WENO5 reconstruction and with the passive CME tracer (state
+and tracer bitwise), and one run is checked against the oracle."""
 import sys
 
 import numpy as np
@@ -110,10 +110,13 @@ def test_ensemble_grid_size_and_repeat_calls(mods):
 
 @pytest.mark.parametrize("phys,persistent", [
     (dict(tracer=True), 1), (dict(tracer=True), 0), (dict(flux=2), 1),
-    (dict(flux=2, limiter=1, tracer=True), 1), (dict(tracer=True, precision=32), 0)])
+    (dict(flux=2, limiter=1, tracer=True), 1), (dict(tracer=True, precision=32), 0),
+    (dict(limiter=2), 1), (dict(limiter=2), 0), (dict(limiter=2, flux=2), 1),
+    (dict(limiter=2, precision=32), 0)])
 def test_ensemble_with_tracer_and_hlld_bitwise_equal_single_runs(mods, phys, persistent):
     """Every run carries a cone CME; with the tracer on, tau of every run is
-    bit-identical to the single run's as well."""
+    bit-identical to the single run's as well.  With WENO5 (limiter 2) the
+    runs use the WENO5 face-once tile, as a single run does."""
     _, solver, _ = mods
     steps = 19
     e, grids = build_ensemble(mods, planes=[8, 5, 3], **phys)

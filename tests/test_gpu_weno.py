@@ -124,9 +124,12 @@ def test_weno5_fp32_close_to_fp64(mods):
         x.close()
 
 
-def test_ensemble_rejects_weno5(mods):
+def test_ensemble_rejects_weno5_with_the_tracer(mods):
+    """The WENO5 tile keeps no face mass fluxes: ensembles run WENO5 without
+    the tracer only (single runs switch to the thread-per-cell kernel)."""
     _, _, abi = mods
     from paper_2501_15923_amd.ensemble import Ensemble
     with pytest.raises(abi.IcarusError) as e:
-        Ensemble([synth.Grid(64, 16, 32)], limiter=WENO5)
+        Ensemble([synth.Grid(64, 16, 32)], limiter=WENO5, tracer=True)
     assert e.value.code == abi.ICR_ERR_UNSUPPORTED
+    Ensemble([synth.Grid(64, 16, 32)], limiter=WENO5).close()
