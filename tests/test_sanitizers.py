@@ -83,7 +83,8 @@ gs = (_abi.IcrGrid * 3)(grid(), grid(n_r=150), grid(n_r=0))
 assert L.icr_ens_workspace_bytes(2, gs, B(phys()), B(n)) == 0
 assert L.icr_ens_workspace_bytes(3, gs, B(phys()), B(n)) == -1
 assert L.icr_ens_workspace_bytes(2, gs, B(phys(tracer=1)), B(n)) == 0
-assert L.icr_ens_workspace_bytes(2, gs, B(phys(limiter=2)), B(n)) == -5
+assert L.icr_ens_workspace_bytes(2, gs, B(phys(limiter=2)), B(n)) == 0
+assert L.icr_ens_workspace_bytes(2, gs, B(phys(limiter=2, tracer=1)), B(n)) == -5
 h = ctypes.c_void_p()
 assert L.icr_create(B(grid()), B(phys()), None, 0, None, B(h)) == -1
 assert L.icr_create(B(grid()), B(phys()), ctypes.c_void_p(256), 10, None, B(h)) == -1
