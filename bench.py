@@ -190,7 +190,7 @@ def relax_bench(args):
     z = np.load(args.weights)
     dims = tuple(int(v) for v in z["dims"])
     g = synth.Grid(dims[2], dims[0], dims[1])
-    net = WarmStartNet(*dims[:6], batch_max=8, phi_lo=dims[6], phi_hi=dims[7])
+    net = WarmStartNet.from_dims(dims, batch_max=8)
     net.set_params(z["params"])
     t_ref = 2.0 * relax.slow_crossing_time(g)
     seeds = list(range(warmstart.TEST_SEED0, warmstart.TEST_SEED0 + args.maps))
@@ -727,7 +727,7 @@ def headline_relax(seed=2000):
     z = np.load(RELAX_WEIGHTS)
     dims = tuple(int(v) for v in z["dims"])
     g = synth.Grid(dims[2], dims[0], dims[1])
-    net = WarmStartNet(*dims[:6], batch_max=1, phi_lo=dims[6], phi_hi=dims[7])
+    net = WarmStartNet.from_dims(dims, batch_max=1)
     net.set_params(z["params"])
     log(f"bench: relaxation plain vs warm on held-out map {seed}, {g.nr}x{g.nt}x{g.np_}")
     row = warmstart.evaluate(net, g, [seed], 2.0 * relax.slow_crossing_time(g),

@@ -8,8 +8,11 @@
  * the plain radial-expansion start (Sect. 2.1) remains the fallback.
  *
  * Network per sample, on the (theta, phi) grid of the map:
- *   features X [n_theta][n_phi][8]  (normalised boundary primitives)
- *   conv 3 x nk 8 -> c1, SiLU, over colatitude offsets -1..1 and longitude
+ *   features X [n_theta][n_phi][C], C = 8 normalised boundary primitives,
+ *   plus (coord = 1) two colatitude channels t and 2 t^2 - 1, t running
+ *   from -1 to 1 across the grid's colatitude range, so the encoder knows
+ *   how far a column sits from the theta boundaries
+ *   conv 3 x nk C -> c1, SiLU, over colatitude offsets -1..1 and longitude
  *   offsets phi_lo..phi_hi (nk = phi_hi - phi_lo + 1): plasma at longitude
  *   phi and radius r left the inner boundary at phi + Omega (r - r_in) / v_r
  *   in the co-rotating frame, so a window reaching far to positive offsets
@@ -21,7 +24,7 @@
  *   units of 100 km/s for velocities, of |B_r|+|B_phi| of the expansion for B).
  * Products: BF16 operands on MFMA with FP32 accumulation.  Parameters: FP32
  * masters (updated by Adam) with BF16 copies used by the products.
- * Parameter vector order: W1 [3*nk*8][c1], b1 [c1], W2 [9*c1][c2], b2 [c2],
+ * Parameter vector order: W1 [3*nk*C][c1], b1 [c1], W2 [9*c1][c2], b2 [c2],
  * W3 [c2][hidden], b3 [hidden], W4 [hidden][n_r*8], b4 [n_r*8]; weights
  * row-major [in][out]; conv input index = tap*C + channel with
  * tap = (dtheta+1)*nk + (dphi-phi_lo) (nk = 3, phi_lo = -1 in the second
@@ -48,6 +51,8 @@ typedef struct {
   int batch_max;            /* samples per forward/backward call          */
   int phi_lo, phi_hi;       /* first-layer longitude offsets, inclusive:
                                phi_lo <= 0 <= phi_hi, window <= n_phi     */
+  int coord;                /* 1: two colatitude input channels (C = 10),
+                               0: none (C = 8)                            */
 } icr_nn_shape;
 
 typedef struct icr_nn icr_nn;
@@ -79,7 +84,9 @@ int icr_nn_adam_step(icr_nn *n, float lr, float beta1, float beta2, float eps);
 
 /* Features of `batch` SI maps [batch][8][n_theta][n_phi] (dev) with
  * colatitude centres thc_dev [n_theta]: ln(rho/rho0), v_r/100 km/s - 5,
- * v_theta/100 km/s, inertial v_phi/100 km/s, ln(p/p0), B/250 nT. */
+ * v_theta/100 km/s, inertial v_phi/100 km/s, ln(p/p0), B/250 nT, then with
+ * coord = 1 the colatitude channels t, 2 t^2 - 1 (t = -1 at the first
+ * colatitude centre, 1 at the last); x_dev [batch][n_theta][n_phi][C]. */
 int icr_nn_encode_map(icr_nn *n, int batch, const double *maps_dev,
                       const double *thc_dev, double omega, double r_in,
                       float *x_dev);

@@ -61,11 +61,12 @@ def col2im(da, B, nt, nph, C, dk0=-1, nk=3):
 
 
 class Shape:
-    def __init__(self, n_theta, n_phi, n_r, c1, c2, hidden, phi_lo=-1, phi_hi=1):
+    def __init__(self, n_theta, n_phi, n_r, c1, c2, hidden, phi_lo=-1, phi_hi=1, coord=0):
         self.nt, self.np_, self.nr = n_theta, n_phi, n_r
         self.c1, self.c2, self.h = c1, c2, hidden
         self.phi_lo, self.nk = phi_lo, phi_hi - phi_lo + 1
-        self.k1 = 3 * self.nk * 8
+        self.cin = 10 if coord else 8  # map features (+ two colatitude channels)
+        self.k1 = 3 * self.nk * self.cin
         self.no = 8 * n_r
         self.sizes = [self.k1 * c1, c1, 9 * c1 * c2, c2, c2 * hidden, hidden, hidden * self.no,
                       self.no]
@@ -136,14 +137,22 @@ V0 = 1e5
 B0 = 250e-9
 
 
-def encode_map(maps, thc, omega, r_in):
-    """maps [B][8][nt][np] SI -> X [B][nt][np][8]."""
+def encode_map(maps, thc, omega, r_in, coord=0):
+    """maps [B][8][nt][np] SI -> X [B][nt][np][C]; with coord the colatitude
+    channels t (linear from -1 at the first to 1 at the last colatitude
+    centre) and 2 t^2 - 1 follow the eight map features."""
     m = np.asarray(maps, dtype=np.float64)
     sth = np.sin(thc)[None, :, None]
-    x = np.stack([np.log(m[:, 0] / RHO0), m[:, 1] / V0 - 5.0, m[:, 2] / V0,
-                  (m[:, 3] + omega * r_in * sth) / V0, np.log(m[:, 4] / P0),
-                  m[:, 5] / B0, m[:, 6] / B0, m[:, 7] / B0], axis=-1)
-    return x
+    feats = [np.log(m[:, 0] / RHO0), m[:, 1] / V0 - 5.0, m[:, 2] / V0,
+             (m[:, 3] + omega * r_in * sth) / V0, np.log(m[:, 4] / P0),
+             m[:, 5] / B0, m[:, 6] / B0, m[:, 7] / B0]
+    if coord:
+        thc = np.asarray(thc, dtype=np.float64)
+        t = ((2.0 * thc - thc[0] - thc[-1]) / (thc[-1] - thc[0]) if len(thc) > 1
+             else np.zeros(1))
+        tt = np.broadcast_to(t[None, :, None], m[:, 0].shape)
+        feats += [tt, 2.0 * tt * tt - 1.0]
+    return np.stack(feats, axis=-1)
 
 
 def radial_base(m, rc, thc, omega, r_in, gamma):

@@ -55,7 +55,8 @@ class IcrStepInfo(ctypes.Structure):
 class NnShape(ctypes.Structure):
     _fields_ = [("n_theta", ctypes.c_int), ("n_phi", ctypes.c_int), ("n_r", ctypes.c_int),
                 ("c1", ctypes.c_int), ("c2", ctypes.c_int), ("hidden", ctypes.c_int),
-                ("batch_max", ctypes.c_int), ("phi_lo", ctypes.c_int), ("phi_hi", ctypes.c_int)]
+                ("batch_max", ctypes.c_int), ("phi_lo", ctypes.c_int), ("phi_hi", ctypes.c_int),
+                ("coord", ctypes.c_int)]
 
 
 class IcarusError(RuntimeError):

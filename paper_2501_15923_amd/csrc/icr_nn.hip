@@ -377,10 +377,11 @@ struct Norm {
   double rho_ref, v_ref, p_ref, b_ref;
 };
 
-// X[b][j][k][f] from SI maps [b][8][nt][np]
+// X[b][j][k][f] from SI maps [b][8][nt][np] (cin = 8, or 10 with the two
+// colatitude channels)
 __global__ void k_encode_map(const double* __restrict__ maps, float* __restrict__ x, int B, int nt,
                              int np, double omega, double r_in, const double* __restrict__ thc,
-                             Norm nz) {
+                             Norm nz, int cin) {
   const long long n = (long long)B * nt * np;
   const long long q = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   if (q >= n) return;
@@ -389,7 +390,12 @@ __global__ void k_encode_map(const double* __restrict__ maps, float* __restrict_
   const int b = (int)(q / ((long long)nt * np));
   const long long plane = (long long)nt * np;
   const double* m = maps + (long long)b * 8 * plane + (long long)j * np + k;
-  float* o = x + q * 8;
+  float* o = x + q * cin;
+  if (cin > 8) {
+    const double t = nt > 1 ? (2.0 * thc[j] - thc[0] - thc[nt - 1]) / (thc[nt - 1] - thc[0]) : 0.0;
+    o[8] = (float)t;
+    o[9] = (float)(2.0 * t * t - 1.0);
+  }
   o[0] = (float)log(m[0] / nz.rho_ref);
   o[1] = (float)(m[1 * plane] / nz.v_ref - 5.0);
   o[2] = (float)(m[2 * plane] / nz.v_ref);
@@ -499,7 +505,7 @@ struct Sizes {
   long long ncol, M;           // columns per sample, rows of a batch
   long long w1, w2, w3, w4;    // weight counts
   long long nparam;
-  int c1, c2, h, no, k1, k2;   // channels, hidden, outputs per column, conv K
+  int cin, c1, c2, h, no, k1, k2;  // input features, channels, hidden, outputs, conv K
 };
 
 Sizes sizes(const icr_nn_shape& s) {
@@ -510,7 +516,8 @@ Sizes sizes(const icr_nn_shape& s) {
   z.c2 = s.c2;
   z.h = s.hidden;
   z.no = s.n_r * 8;
-  z.k1 = 3 * (s.phi_hi - s.phi_lo + 1) * 8;
+  z.cin = s.coord ? 10 : 8;
+  z.k1 = 3 * (s.phi_hi - s.phi_lo + 1) * z.cin;
   z.k2 = 9 * s.c1;
   z.w1 = (long long)z.k1 * z.c1;
   z.w2 = (long long)z.k2 * z.c2;
@@ -523,7 +530,7 @@ Sizes sizes(const icr_nn_shape& s) {
 int check_shape(const icr_nn_shape* s) {
   if (!s) return nfail(ICR_NN_ERR_ARG, "shape is NULL");
   if (s->n_theta < 1 || s->n_phi < 3 || s->n_r < 1 || s->c1 < 1 || s->c2 < 1 || s->hidden < 1 ||
-      s->batch_max < 1)
+      s->batch_max < 1 || (s->coord != 0 && s->coord != 1))
     return nfail(ICR_NN_ERR_ARG, "invalid network shape");
   if (s->phi_lo > 0 || s->phi_hi < 0 || s->phi_hi - s->phi_lo + 1 > s->n_phi)
     return nfail(ICR_NN_ERR_ARG, "first-layer longitude window must hold offset 0 and fit n_phi");
@@ -573,8 +580,8 @@ size_t layout(const icr_nn_shape& s, icr_nn* n) {
   float* m = (float*)take(4 * P);
   float* v = (float*)take(4 * P);
   uint16_t* pb = (uint16_t*)take(2 * P);
-  float* x = (float*)take(4 * M * 8);
-  uint16_t* xb = (uint16_t*)take(2 * M * 8);
+  float* x = (float*)take(4 * M * z.cin);
+  uint16_t* xb = (uint16_t*)take(2 * M * z.cin);
   uint16_t* a1 = (uint16_t*)take(2 * M * z.k1);
   float* z1 = (float*)take(4 * M * z.c1);
   uint16_t* h1 = (uint16_t*)take(2 * M * z.c1);
@@ -646,8 +653,8 @@ void forward(icr_nn* n, int B, const float* x_dev) {
   const int nt = n->s.n_theta, np = n->s.n_phi;
   const long long M = (long long)B * z.ncol;
   hipStream_t s = n->stream;
-  hipLaunchKernelGGL(k_to_bf16, g1(M * 8), dim3(256), 0, s, x_dev, n->xb, M * 8);
-  hipLaunchKernelGGL(k_im2col, g1(M * z.k1), dim3(256), 0, s, n->xb, n->a1, B, nt, np, 8,
+  hipLaunchKernelGGL(k_to_bf16, g1(M * z.cin), dim3(256), 0, s, x_dev, n->xb, M * z.cin);
+  hipLaunchKernelGGL(k_im2col, g1(M * z.k1), dim3(256), 0, s, n->xb, n->a1, B, nt, np, z.cin,
                      n->s.phi_lo, n->s.phi_hi - n->s.phi_lo + 1);
   gemm(0, 0, n->a1, n->W1b, n->z1, n->b1, (int)M, z.c1, z.k1, z.k1, z.c1, z.c1, s);
   hipLaunchKernelGGL(k_silu, g1(M * z.c1), dim3(256), 0, s, n->z1, n->h1, M * z.c1);
@@ -800,7 +807,7 @@ int icr_nn_encode_map(icr_nn* n, int batch, const double* maps_dev, const double
   const Norm nz{1.67262192369e-27 * 1e8, 1e5, 2.0 * 1e8 * 1.380649e-23 * 1e6, 250e-9};
   const long long q = (long long)batch * n->z.ncol;
   hipLaunchKernelGGL(k_encode_map, g1(q), dim3(256), 0, n->stream, maps_dev, x_dev, batch,
-                     n->s.n_theta, n->s.n_phi, omega, r_in, thc_dev, nz);
+                     n->s.n_theta, n->s.n_phi, omega, r_in, thc_dev, nz, n->z.cin);
   NN_TRY(hipGetLastError());
   return ICR_NN_OK;
 }

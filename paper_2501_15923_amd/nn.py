@@ -25,12 +25,25 @@ def _p(t):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def init_params(n_theta, n_phi, n_r, c1, c2, hidden, phi_lo=-1, phi_hi=1, seed=0):
+def in_channels(coord):
+    """Input features per column: 8 boundary primitives (+ 2 colatitude channels)."""
+    return 10 if coord else 8
+
+
+def full_dims(dims):
+    """(n_theta, n_phi, n_r, c1, c2, hidden, phi_lo, phi_hi, coord) from a
+    stored dims vector (files written before the colatitude channels hold 8
+    entries: coord 0)."""
+    d = tuple(int(v) for v in dims)
+    return d + (0,) if len(d) == 8 else d
+
+
+def init_params(n_theta, n_phi, n_r, c1, c2, hidden, phi_lo=-1, phi_hi=1, coord=0, seed=0):
     """Scaled normal weights (variance 1/fan_in), zero biases; the last layer
     starts small so the initial output is close to the radial expansion."""
     rng = np.random.default_rng(seed)
     no = 8 * n_r
-    k1 = 3 * (phi_hi - phi_lo + 1) * 8
+    k1 = 3 * (phi_hi - phi_lo + 1) * in_channels(coord)
     parts = []
     for fan_in, fan_out, scale in ((k1, c1, 1.0), (9 * c1, c2, 1.0), (c2, hidden, 1.0),
                                    (hidden, no, 0.1)):
@@ -41,11 +54,13 @@ def init_params(n_theta, n_phi, n_r, c1, c2, hidden, phi_lo=-1, phi_hi=1, seed=0
 
 class WarmStartNet:
     def __init__(self, n_theta, n_phi, n_r, c1=64, c2=128, hidden=384, batch_max=8,
-                 phi_lo=-1, phi_hi=1, device=0, stream=None):
+                 phi_lo=-1, phi_hi=1, coord=0, device=0, stream=None):
         import torch
         self.torch = torch
-        self.shape = NnShape(n_theta, n_phi, n_r, c1, c2, hidden, batch_max, phi_lo, phi_hi)
-        self.dims = (n_theta, n_phi, n_r, c1, c2, hidden, phi_lo, phi_hi)
+        self.shape = NnShape(n_theta, n_phi, n_r, c1, c2, hidden, batch_max, phi_lo, phi_hi,
+                             coord)
+        self.dims = (n_theta, n_phi, n_r, c1, c2, hidden, phi_lo, phi_hi, coord)
+        self.cin = in_channels(coord)
         self.device = torch.device("cuda", device)
         n = ctypes.c_longlong()
         _check(lib().icr_nn_param_count(ctypes.byref(self.shape), ctypes.byref(n)))
@@ -85,8 +100,15 @@ class WarmStartNet:
         _check(lib().icr_nn_get_params(self.h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
         return out
 
+    @classmethod
+    def from_dims(cls, dims, batch_max=8, **kw):
+        """The network of a stored dims vector (8 or 9 entries)."""
+        nt, nph, nr, c1, c2, h, lo, hi, coord = full_dims(dims)
+        return cls(nt, nph, nr, c1, c2, h, batch_max=batch_max, phi_lo=lo, phi_hi=hi,
+                   coord=coord, **kw)
+
     def forward(self, x):
-        """x: torch float32 [B][nt][np][8] on the device -> y [B*ncol][no]."""
+        """x: torch float32 [B][nt][np][C] on the device -> y [B*ncol][no]."""
         B = x.shape[0]
         y = self.torch.empty((B * self.ncol, self.no), dtype=self.torch.float32,
                              device=self.device)
@@ -108,7 +130,7 @@ class WarmStartNet:
     def encode_map(self, maps, thc, omega, r_in):
         """maps: torch float64 [B][8][nt][np] SI on the device; thc: [nt]."""
         B = maps.shape[0]
-        x = self.torch.empty((B, self.shape.n_theta, self.shape.n_phi, 8),
+        x = self.torch.empty((B, self.shape.n_theta, self.shape.n_phi, self.cin),
                              dtype=self.torch.float32, device=self.device)
         _check(lib().icr_nn_encode_map(self.h, B, _abi.dptr(maps.data_ptr()),
                                        _abi.dptr(thc.data_ptr()), omega, r_in, _p(x)))

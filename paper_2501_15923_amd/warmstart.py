@@ -25,6 +25,7 @@ import time
 import numpy as np
 
 from . import relax, synth
+from .nn import full_dims, in_channels
 from .synth import AU, Grid
 
 TRAIN_SEED0, TEST_SEED0 = 1000, 2000
@@ -104,7 +105,7 @@ def _relaxed_single(grid, seeds, t_ref, precision, chunk):
 def build_dataset(net, grid, seeds, t_ref, rc, thc, precision=64, batch=64):
     import torch
     n = len(seeds)
-    X = torch.empty((n, grid.nt, grid.np_, 8), dtype=torch.float32, device="cuda")
+    X = torch.empty((n, grid.nt, grid.np_, net.cin), dtype=torch.float32, device="cuda")
     T = torch.empty((n, grid.nt * grid.np_, 8 * grid.nr), dtype=torch.float32, device="cuda")
     M = torch.empty((n, 8, grid.nt, grid.np_), dtype=torch.float64, device="cuda")
     q = 0
@@ -123,8 +124,8 @@ def scale_output(params, dims, s):
     scaled the same way weights the squared error of that output by s^2 (the
     last layer is linear); dividing by s afterwards returns the usual
     output."""
-    nt, nph, nr, c1, c2, hidden, lo, hi = (int(d) for d in dims)
-    k1 = 3 * (hi - lo + 1) * 8
+    nt, nph, nr, c1, c2, hidden, lo, hi, coord = full_dims(dims)
+    k1 = 3 * (hi - lo + 1) * in_channels(coord)
     no = 8 * nr
     p = np.array(params, dtype=np.float32, copy=True)
     off = k1 * c1 + c1 + 9 * c1 * c2 + c2 + c2 * hidden + hidden
@@ -138,16 +139,20 @@ def scale_output(params, dims, s):
     return p
 
 
-def widen_params(params, dims, c1, c2, hidden, seed=0):
-    """Grow the encoder channels and the decoder width without changing the
-    network's function: the new units get random incoming weights (the
-    spread of the existing ones, zero biases) and zero outgoing weights, so
-    every output is unchanged until training moves them.  Returns (params,
-    dims) of the wider network."""
-    nt, nph, nr, a1, a2, ah, lo, hi = (int(d) for d in dims)
-    assert c1 >= a1 and c2 >= a2 and hidden >= ah
+def widen_params(params, dims, c1, c2, hidden, coord=None, seed=0):
+    """Grow the encoder channels and the decoder width, and optionally add
+    the colatitude input channels, without changing the network's function:
+    the new units get random incoming weights (the spread of the existing
+    ones, zero biases) and zero outgoing weights, and the new input channels
+    zero first-layer weights, so every output is unchanged until training
+    moves them.  Returns (params, dims) of the wider network."""
+    nt, nph, nr, a1, a2, ah, lo, hi, acoord = full_dims(dims)
+    coord = acoord if coord is None else int(coord)
+    assert c1 >= a1 and c2 >= a2 and hidden >= ah and coord >= acoord
     rng = np.random.default_rng(seed)
-    k1 = 3 * (hi - lo + 1) * 8
+    taps = 3 * (hi - lo + 1)
+    ain, cin = in_channels(acoord), in_channels(coord)
+    k1 = taps * ain
     no = 8 * nr
     p = np.asarray(params, dtype=np.float32)
     shapes = [(k1, a1), (a1,), (9, a1, a2), (a2,), (a2, ah), (ah,), (ah, no), (no,)]
@@ -164,7 +169,11 @@ def widen_params(params, dims, c1, c2, hidden, seed=0):
         out = out.astype(np.float32)
         out[tuple(slice(0, s) for s in w.shape)] = w
         return out
-    nW1 = grow(W1, (k1, c1), float(W1.std()))
+    # first layer rows are tap * C + channel: the old channels keep their
+    # taps, the new input channels start at zero
+    W1 = W1.reshape(taps, ain, a1)
+    nW1 = grow(W1, (taps, cin, c1), float(W1.std()))
+    nW1[:, ain:, :] = 0.0
     nb1 = grow(b1, (c1,), 0.0)
     nW2 = grow(W2, (9, c1, c2), float(W2.std()))
     nW2[:, a1:, :] = 0.0          # new first-layer channels feed nothing yet
@@ -174,7 +183,7 @@ def widen_params(params, dims, c1, c2, hidden, seed=0):
     nb3 = grow(b3, (hidden,), 0.0)
     nW4 = grow(W4, (hidden, no), 0.0)  # new decoder units feed nothing yet
     q = np.concatenate([a.ravel() for a in (nW1, nb1, nW2, nb2, nW3, nb3, nW4, b4)])
-    return q.astype(np.float32), (nt, nph, nr, c1, c2, hidden, lo, hi)
+    return q.astype(np.float32), (nt, nph, nr, c1, c2, hidden, lo, hi, coord)
 
 
 class PlainCache:
@@ -330,6 +339,9 @@ def main(argv=None):
     ap.add_argument("--c1", type=int, default=64)
     ap.add_argument("--c2", type=int, default=128)
     ap.add_argument("--hidden", type=int, default=384)
+    ap.add_argument("--coord", type=int, default=0,
+                    help="1: two colatitude input channels (grown into --init-weights "
+                         "with zero first-layer weights)")
     ap.add_argument("--phi-lo", type=int, default=None)
     ap.add_argument("--phi-hi", type=int, default=None)
     ap.add_argument("--lr", type=float, default=2e-3)
@@ -374,16 +386,18 @@ def main(argv=None):
     lo, hi = default_window(g)
     lo = lo if args.phi_lo is None else args.phi_lo
     hi = hi if args.phi_hi is None else args.phi_hi
-    dims = (g.nt, g.np_, g.nr, args.c1, args.c2, args.hidden, lo, hi)
+    dims = (g.nt, g.np_, g.nr, args.c1, args.c2, args.hidden, lo, hi, args.coord)
     src = args.weights or args.init_weights
     p_widened = None
     if src:
-        dims = tuple(int(v) for v in np.load(src)["dims"])
+        dims = full_dims(np.load(src)["dims"])
         assert dims[:3] == (g.nt, g.np_, g.nr), "weights for another grid"
-        if args.widen and not args.weights:
-            w1, w2, wh = (int(v) for v in args.widen.split(","))
-            p_widened, dims = widen_params(np.load(src)["params"], dims, w1, w2, wh)
-    net = WarmStartNet(*dims[:6], batch_max=8, phi_lo=dims[6], phi_hi=dims[7])
+        if (args.widen or args.coord > dims[8]) and not args.weights:
+            w1, w2, wh = ((int(v) for v in args.widen.split(",")) if args.widen
+                          else dims[3:6])
+            p_widened, dims = widen_params(np.load(src)["params"], dims, w1, w2, wh,
+                                           coord=max(args.coord, dims[8]))
+    net = WarmStartNet.from_dims(dims, batch_max=8)
     p0 = init_params(*net.dims, seed=0)
     probe = Solver(g)
     rc, thc = grid_geometry(probe)
@@ -411,6 +425,7 @@ def main(argv=None):
         if p_widened is not None:
             p_init = p_widened
         report["widen"] = args.widen
+        report["coord"] = net.dims[8]
         osc = np.ones(8 * g.nr)
         osc[0::8] = math.sqrt(args.rho_weight)
         rc_au = rc.cpu().numpy() / synth.AU

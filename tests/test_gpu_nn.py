@@ -48,9 +48,10 @@ def test_gemm_bf16_layouts(torch, ta, tb, M, N, K):
 SHAPE = dict(n_theta=6, n_phi=10, n_r=5, c1=8, c2=16, hidden=24)
 
 
-def small_net(torch, batch=2, seed=0, window=(-1, 1)):
+def small_net(torch, batch=2, seed=0, window=(-1, 1), coord=0):
     from paper_2501_15923_amd.nn import WarmStartNet, init_params
-    net = WarmStartNet(**SHAPE, batch_max=batch, phi_lo=window[0], phi_hi=window[1])
+    net = WarmStartNet(**SHAPE, batch_max=batch, phi_lo=window[0], phi_hi=window[1],
+                       coord=coord)
     p = init_params(*net.dims, seed=seed)
     p[-8 * SHAPE["n_r"] - SHAPE["hidden"] * 8 * SHAPE["n_r"]:] *= 10  # non-trivial outputs
     net.set_params(p)
@@ -58,14 +59,15 @@ def small_net(torch, batch=2, seed=0, window=(-1, 1)):
     return net, sh, p.astype(np.float64)
 
 
-WINDOWS = [(-1, 1), (-2, 5)]
+# (phi_lo, phi_hi, colatitude channels)
+WINDOWS = [(-1, 1, 0), (-2, 5, 0), (-2, 5, 1)]
 
 
 @pytest.mark.parametrize("window", WINDOWS)
 def test_forward_matches_oracle(torch, window):
-    net, sh, p = small_net(torch, window=window)
+    net, sh, p = small_net(torch, window=window[:2], coord=window[2])
     rng = np.random.default_rng(7)
-    x = rng.normal(size=(2, 6, 10, 8))
+    x = rng.normal(size=(2, 6, 10, sh.cin))
     y = net.forward(torch.from_numpy(x.astype(np.float32)).cuda()).cpu().numpy()
     ref, _ = no.forward(sh, p.astype(np.float32).astype(np.float64), x.astype(np.float32))
     assert np.linalg.norm(y - ref) / np.linalg.norm(ref) < 5e-3
@@ -73,9 +75,9 @@ def test_forward_matches_oracle(torch, window):
 
 @pytest.mark.parametrize("window", WINDOWS)
 def test_gradients_match_oracle(torch, window):
-    net, sh, p = small_net(torch, window=window)
+    net, sh, p = small_net(torch, window=window[:2], coord=window[2])
     rng = np.random.default_rng(8)
-    x = rng.normal(size=(2, 6, 10, 8)).astype(np.float32)
+    x = rng.normal(size=(2, 6, 10, sh.cin)).astype(np.float32)
     t = rng.normal(0, 0.5, (2 * 60, sh.no)).astype(np.float32)
     loss, g = net.loss_grad(torch.from_numpy(x).cuda(), torch.from_numpy(t).cuda(),
                             want_grad=True)
@@ -128,6 +130,11 @@ def test_transforms_match_oracle(torch):
     drc = torch.from_numpy(rc).cuda()
     x = net.encode_map(dm, dth, om, rin).cpu().numpy()
     assert np.allclose(x, no.encode_map(m[None], th, om, rin), rtol=1e-5, atol=1e-6)
+    netc = WarmStartNet(g.nt, g.np_, g.nr, 8, 16, 24, batch_max=1, coord=1)
+    xc = netc.encode_map(dm, dth, om, rin).cpu().numpy()
+    assert xc.shape[-1] == 10
+    assert np.allclose(xc, no.encode_map(m[None], th, om, rin, coord=1), rtol=1e-5, atol=1e-6)
+    netc.close()
     rng = np.random.default_rng(6)
     y = rng.normal(0, 0.2, (g.nt * g.np_, 8 * g.nr)).astype(np.float32)
     st = net.decode_state(dm[0], torch.from_numpy(y).cuda(), drc, dth, om, rin).cpu().numpy()

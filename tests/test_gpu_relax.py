@@ -150,7 +150,7 @@ def test_committed_warm_start_relaxes_faster(mods):
     z = np.load(path)
     dims = tuple(int(v) for v in z["dims"])
     g = synth.Grid(dims[2], dims[0], dims[1])
-    net = WarmStartNet(*dims[:6], batch_max=1, phi_lo=dims[6], phi_hi=dims[7])
+    net = WarmStartNet.from_dims(dims, batch_max=1)
     net.set_params(z["params"])
     t_ref = 2.0 * relax.slow_crossing_time(g)
     say("warm start with committed weights, held-out seed 2031")
@@ -186,7 +186,7 @@ def test_committed_production_warm_start_relaxes_faster(mods):
     dims = tuple(int(v) for v in z["dims"])
     g = synth.Grid(dims[2], dims[0], dims[1])
     assert (g.nr, g.nt, g.np_) == (600, 60, 120)
-    net = WarmStartNet(*dims[:6], batch_max=1, phi_lo=dims[6], phi_hi=dims[7])
+    net = WarmStartNet.from_dims(dims, batch_max=1)
     net.set_params(z["params"])
     t_ref = 2.0 * relax.slow_crossing_time(g)
     say("production-grid warm start with committed weights, held-out seed 2031")

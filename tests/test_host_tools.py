@@ -145,7 +145,7 @@ def test_widened_network_keeps_its_function_and_trains_every_new_weight():
     rng = np.random.default_rng(0)
     p = (p + 0.05 * rng.standard_normal(p.size)).astype(np.float32)  # non-zero biases too
     q, d2 = widen_params(p, dims, 5, 7, 9, seed=1)
-    assert d2 == (5, 8, 4, 5, 7, 9, -1, 2)
+    assert d2 == (5, 8, 4, 5, 7, 9, -1, 2, 0)
     s1 = O.Shape(*dims[:6], phi_lo=dims[6], phi_hi=dims[7])
     s2 = O.Shape(*d2[:6], phi_lo=d2[6], phi_hi=d2[7])
     assert q.size == s2.nparam
@@ -165,6 +165,36 @@ def test_widened_network_keeps_its_function_and_trains_every_new_weight():
     assert np.abs(G[6][6:]).max() > 0          # new decoder rows (outgoing)
     assert np.abs(G[4][4:]).max() > 0          # new second-layer channels (outgoing)
     assert np.abs(G[2].reshape(9, 5, 7)[:, 3:, :]).max() > 0  # new first-layer channels
+
+
+def test_colatitude_channels_grown_into_a_trained_network():
+    """Adding the two colatitude input channels with zero first-layer weights
+    keeps the function: the oracle gives the same outputs on the features
+    with and without them, the old first-layer rows keep their taps, and the
+    new rows receive a gradient."""
+    sys.path.insert(0, os.path.join(ROOT, "oracle"))
+    import nn_oracle as O
+    from paper_2501_15923_amd.nn import init_params
+    from paper_2501_15923_amd.warmstart import widen_params
+    dims = (5, 8, 4, 3, 4, 6, -1, 2)
+    p = init_params(*dims[:6], phi_lo=dims[6], phi_hi=dims[7], seed=4)
+    rng = np.random.default_rng(1)
+    p = (p + 0.05 * rng.standard_normal(p.size)).astype(np.float32)
+    q, d2 = widen_params(p, dims, 3, 4, 6, coord=1)
+    assert d2 == (5, 8, 4, 3, 4, 6, -1, 2, 1)
+    s1 = O.Shape(*dims[:8])
+    s2 = O.Shape(*d2)
+    assert s2.cin == 10 and q.size == s2.nparam
+    x8 = rng.standard_normal((2, 5, 8, 8))
+    x10 = np.concatenate([x8, rng.standard_normal((2, 5, 8, 2))], axis=-1)
+    y1, _ = O.forward(s1, p.astype(np.float64), x8, bf16=False)
+    y2, _ = O.forward(s2, q.astype(np.float64), x10, bf16=False)
+    assert np.allclose(y1, y2, rtol=0, atol=1e-12)
+    W1o, W1n = s1.unpack(p)[0], s2.unpack(q)[0].reshape(-1, 10, 3)
+    assert np.array_equal(W1n[:, :8, :].reshape(-1, 3), W1o) and not W1n[:, 8:, :].any()
+    t = rng.standard_normal(y2.shape)
+    _, g = O.loss_grad(s2, q.astype(np.float64), x10, t, bf16=False)
+    assert np.abs(s2.unpack(g)[0].reshape(-1, 10, 3)[:, 8:, :]).max() > 0
 
 
 def test_plain_cache_round_trip(tmp_path):

@@ -9,16 +9,16 @@ from oracle import nn_oracle as no
 from paper_2501_15923_amd import synth
 
 
-def tiny(phi_lo=-1, phi_hi=1):
-    sh = no.Shape(4, 6, 3, 4, 5, 6, phi_lo, phi_hi)
+def tiny(phi_lo=-1, phi_hi=1, coord=0):
+    sh = no.Shape(4, 6, 3, 4, 5, 6, phi_lo, phi_hi, coord)
     rng = np.random.default_rng(1)
     p = rng.normal(0, 0.4, sh.nparam)
-    x = rng.normal(0, 1, (2, 4, 6, 8))
+    x = rng.normal(0, 1, (2, 4, 6, sh.cin))
     t = rng.normal(0, 0.3, (2 * 4 * 6, sh.no))
     return sh, p, x, t
 
 
-@pytest.mark.parametrize("window", [(-1, 1), (-2, 3)])
+@pytest.mark.parametrize("window", [(-1, 1, 0), (-2, 3, 0), (-1, 2, 1)])
 def test_backward_matches_finite_differences(window):
     sh, p, x, t = tiny(*window)
     loss, g = no.loss_grad(sh, p, x, t, bf16=False)
@@ -86,4 +86,14 @@ def test_transforms_round_trip():
     x = no.encode_map(m[None], th, om, rin)
     # inertial v_phi of the map vanishes (plasma not rotating at r_in)
     assert np.max(np.abs(x[..., 3])) < 1e-9
+    # the colatitude channels: -1 and 1 at the first and last row, 0 on the
+    # mid row of an odd count, a parabola that is -1 there and 1 at the ends;
+    # the map features are unchanged
+    xc = no.encode_map(m[None], th, om, rin, coord=1)
+    assert xc.shape[-1] == 10 and np.array_equal(xc[..., :8], x)
+    t = xc[0, :, 0, 8]
+    assert abs(t[0] + 1) < 1e-14 and abs(t[-1] - 1) < 1e-14
+    assert np.allclose(t, t[::-1] * -1, atol=1e-14) and np.all(np.diff(t) > 0)
+    assert np.allclose(xc[0, :, :, 9], 2 * xc[0, :, :, 8] ** 2 - 1, atol=1e-14)
+    assert np.allclose(xc[0, :, 3, 8:], xc[0, :, 0, 8:])  # the same for every longitude
     assert np.allclose(np.exp(x[..., 0]) * no.RHO0, np.transpose(m[0])[None].transpose(0, 2, 1))
