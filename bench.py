@@ -739,7 +739,7 @@ def headline_relax(seed=2000):
             "warm_steps": wm["steps"], "warm_wall_s": wm["wall"],
             "ratio": (wm["wall"] / p["wall"]) if p.get("converged") and wm["converged"] else None,
             "target": "<= 1/3",
-            "note": "one held-out map; the median over 32 held-out maps is 0.415 "
+            "note": "one held-out map; the median over 32 held-out maps is 0.324 "
                     "(profiles/warmstart_relax_600x60x120.md)"}
 
 
