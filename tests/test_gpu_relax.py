@@ -167,11 +167,11 @@ def test_committed_warm_start_relaxes_faster(mods):
 
 def test_committed_production_warm_start_relaxes_faster(mods):
     """The committed 600 x 60 x 120 network on held-out map 2031: the warm
-    start relaxes in at most 0.45 of the plain steps (measured 3950 of 12100)
+    start relaxes in at most 0.45 of the plain steps (measured 3500 of 12100)
     and at most half of the plain wall time, network and upload included.
     The convergence criterion is the L2 error over the 1 AU shell; the
     largest pointwise errors at the relaxed check are recorded beside it
-    (measured 11.8 % in rho, at a stream interface, and 1.4 % in v_r) and
+    (measured 11.8 % in rho, at a stream interface, and 1.0 % in v_r) and
     must stay below 15 %."""
     import os
 
