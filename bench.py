@@ -507,6 +507,17 @@ def ingest_counters(dirs, precision, out_path, launch=None):
     print(json.dumps(rec), flush=True)
 
 
+def traffic_for(path, precision, flux, limiter, launch):
+    """The counter record of the current stage-kernel source for this
+    precision, scheme and launch shape [tile_r, planes] (a record holds only
+    for the kernel, scheme and launch it was taken on), or None."""
+    match = [tr for tr in traffic_records(path)
+             if tr.get("precision") == precision and tr.get("kernel_rev") == kernel_rev()
+             and tr.get("flux", "tvdlf") == flux and tr.get("limiter", "minmod") == limiter
+             and tr.get("launch") in (None, list(launch))]
+    return match[-1] if match else None
+
+
 def traffic_records(path):
     """The counter records of a traffic file (a single record or {"records": [...]})."""
     if not os.path.exists(path):
@@ -647,15 +658,9 @@ def main():
     valu = None
     if os.path.exists(args.traffic):
         try:
-            # a record holds for the kernel, scheme and launch shape it was taken on
-            match = [tr for tr in traffic_records(args.traffic)
-                     if tr.get("precision") == args.precision
-                     and tr.get("kernel_rev") == kernel_rev()
-                     and tr.get("flux", "tvdlf") == args.flux
-                     and tr.get("limiter", "minmod") == args.limiter
-                     and tr.get("launch") in (None, [tile_r or 64, planes or 8])]
-            if match:
-                tr = match[-1]
+            tr = traffic_for(args.traffic, args.precision, args.flux, args.limiter,
+                             [tile_r or 64, planes or 8])
+            if tr is not None:
                 traffic = tr.get("bytes_per_launch")
                 vi = tr.get("valu_wave_instr_per_launch")
                 if vi:

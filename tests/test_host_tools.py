@@ -74,6 +74,11 @@ def test_ingest_counters_scales_by_the_copy_and_adds_valu(tmp_path):
     bench.ingest_counters(d[:4], 64, out, "64,15")
     recs = bench.traffic_records(out)
     assert [r["launch"] for r in recs] == [[64, 12], [64, 15]]
+    # the bench picks the record of its own launch shape, scheme and precision
+    assert bench.traffic_for(out, 64, "tvdlf", "minmod", [64, 15])["launch"] == [64, 15]
+    assert bench.traffic_for(out, 64, "tvdlf", "minmod", [64, 8]) is None
+    assert bench.traffic_for(out, 64, "hlld", "minmod", [64, 12]) is None
+    assert bench.traffic_for(out, 32, "tvdlf", "minmod", [64, 12]) is None
     # a file holding one bare record still reads
     json.dump(rec, open(out, "w"))
     assert bench.traffic_records(out) == [rec]
