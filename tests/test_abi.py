@@ -95,3 +95,25 @@ def test_units_match_the_oracle(lib):
     assert lib.lib().icr_units(out.ctypes.data_as(lib.D)) == 0
     u = oracle.units()
     assert np.allclose(out, [u["t"], u["L"], u["rho"], u["p"], u["B"], u["v"]], rtol=1e-15)
+
+
+def test_network_shape_validation_and_parameter_count(lib):
+    """icr_nn_param_count checks the shape on the host: the colatitude flag is
+    0 or 1, and with it the first layer reads 10 features instead of 8 (the
+    count grows by 3 * nk * 2 * c1); the other layers do not change."""
+    L = lib.lib()
+    n = ctypes.c_longlong()
+
+    def count(**kw):
+        d = dict(n_theta=60, n_phi=120, n_r=600, c1=64, c2=128, hidden=384, batch_max=8,
+                 phi_lo=-2, phi_hi=46, coord=0)
+        d.update(kw)
+        rc = L.icr_nn_param_count(ctypes.byref(lib.NnShape(**d)), ctypes.byref(n))
+        return rc, n.value
+
+    rc0, p0 = count()
+    assert rc0 == 0 and p0 == 2046720  # the network without the channels
+    rc1, p1 = count(coord=1)
+    assert rc1 == 0 and p1 - p0 == 3 * 49 * 2 * 64 and p1 == 2065536
+    assert count(coord=2)[0] == -1  # ICR_NN_ERR_ARG
+    assert count(phi_lo=1)[0] != 0 and count(c1=0)[0] != 0
